@@ -1,0 +1,180 @@
+"""Benchmark: GAME training generations on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: 200,000 patterns x 20 features (mixture of three Gaussians clipped
+to [-1, 1]), Legendre expansion of degree 8 (161 genes), population 2,048,
+regression target; synthetic, seeded.  One step is one generation of the
+training loop: fitness of the whole population over all patterns, ranking
+and stop test, and the genetic step (elitism, tournament, crossover,
+mutation).  Inputs are resident in GPU memory before timing starts.
+
+Prints one JSON line with whole-job throughput (chromosome x pattern
+evaluations per second), the fitness kernel's position on the MFMA roofline
+(timed with HIP events on the library's stream), and the CPU oracle timed on
+a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "chromosome×pattern evals/s (% MFMA peak); time-to-target MSE, plain vs chosen"
+FP32_MFMA_PEAK_TFLOPS = 157.3
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fitness_f32_scale_traffic.json")
+
+
+def cpu_baseline(prob, P, seconds=10.0):
+    """The oracle on the host: float64 fitness (expansion then a BLAS
+    product) of a 128-chromosome batch over every pattern, repeated for about
+    `seconds`, plus one oracle genetic step of the whole population; scaled
+    to one generation."""
+    from oracle import ga as oga
+    from oracle import game as og
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    rng = np.random.default_rng(1)
+    batch = 128
+    W = rng.uniform(-1, 1, (batch, prob.n_genes)).astype(np.float32)
+    n_batches = 0
+    t0 = time.perf_counter()
+    while True:
+        og.fitness(prob.X, prob.t, W, prob.basis, prob.degree)
+        n_batches += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    t_fit = (time.perf_counter() - t0) / n_batches
+    pop = rng.uniform(-1, 1, (P, prob.n_genes)).astype(np.float32)
+    fit = rng.uniform(0, 1, P).astype(np.float32)
+    t1 = time.perf_counter()
+    oga.ga_next(pop, fit, 1, oga.GAConfig(population=P))
+    t_ga = time.perf_counter() - t1
+    t_gen = t_fit * (P / batch) + t_ga
+    return {"value": P * prob.n_patterns / t_gen, "unit": "evals/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"{n_batches} float64 fitness batches of {batch} chromosomes x "
+                      f"{prob.n_patterns} patterns ({t_fit:.2f} s each) + one genetic step of "
+                      f"{P} x {prob.n_genes} genes ({t_ga:.2f} s); scaled to one generation "
+                      f"of {P} chromosomes"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain elementwise kernel of known traffic (256 MiB read, "
+                         "256 MiB written per launch) to scale hardware byte counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.calibrate_copy:
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "torch.neg float32", "bytes_read": x.numel() * 4,
+                          "bytes_written": y.numel() * 4, "launches": 5}), flush=True)
+        return
+    from paper_1304_0597_amd import datagen
+    from paper_1304_0597_amd import game as gg
+
+    gg.lib()
+    prob = datagen.scale()
+    P = prob.population
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(prob.X).to(dev)
+    t = torch.from_numpy(prob.t).to(dev)
+    cfg = gg.config(basis=prob.basis, degree=prob.degree, population=P, tournament_k=3,
+                    elitism=2, p_crossover=0.9, p_mutation=0.05, sigma_mutation=0.1, seed=0,
+                    max_generations=1 << 30, target=-1.0)
+    game = gg.Game(cfg, X, t)
+    game.init_population()
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        game.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        game.step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = game.state()
+    assert st["stopped"] == 0, "the run stopped inside the timed region"
+    ms_per_step = elapsed * 1e3 / args.steps
+    evals = P * prob.n_patterns * args.steps
+    value = evals / elapsed
+
+    # Dominant kernel: the fused fitness launch (plus its tiny finish kernel)
+    # on the same stream and launch configuration, timed with HIP events.
+    pop, _ = game.population()
+    f32 = torch.empty(P, dtype=torch.float32, device=dev)
+    reps = max(10, args.steps)
+    game.fitness(pop)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        gg.game_fitness(game.h, pop, P, f32)
+    end.record(stream)
+    end.synchronize()
+    t_kernel = start.elapsed_time(end) / 1e3 / reps
+    Kf = prob.n_genes - 1
+    flops = 2.0 * Kf * P * prob.n_patterns
+    achieved = flops / t_kernel / 1e12
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        try:
+            traffic = json.load(open(PROFILE_TRAFFIC)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "scale: 200,000 patterns x 20 features, Legendre degree 8 "
+                               "(161 genes), population 2,048, one generation per step",
+                   "n_patterns": prob.n_patterns, "n_features": prob.n_features,
+                   "degree": prob.degree, "basis": "legendre", "population": P,
+                   "genes": prob.n_genes},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                     "traffic": traffic, "kernel_ms": t_kernel * 1e3,
+                     "flops_per_launch": flops},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, P)
+    game.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * game.h - C ABI of libgame, GAME genetic-algorithm fitness on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Method: Cavuoti et al., "Astrophysical data mining with GPU. A case study:
+ * genetic classification of globular clusters" (GAME).  A chromosome's genes
+ * weight a per-feature polynomial expansion of degree d (Eq. 1; Eq. 8 for
+ * the trigonometric one), summed over the N features of a pattern plus one
+ * bias (Eq. 2); its fitness is the error of those outputs against the
+ * targets over all NP patterns (MSE Eq. 4, RMSE Eq. 5, TMSE Eq. 10).  The
+ * genetic loop of Sec. 4.1 (generate, evaluate and sort, test the stop
+ * criteria, evolve) runs entirely on the device.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns GAME_OK (0) or a negative game_status and never
+ *    throws; game_last_error() gives a message for the calling thread.
+ *  - "_dev" pointers are device memory owned by the caller (the library
+ *    never allocates device memory); "_host" pointers are host memory.
+ *  - Work is queued on the caller's HIP stream (hipStream_t passed as
+ *    void*; NULL is the default stream) and is asynchronous unless a
+ *    function says it synchronises.
+ *  - Matrices are row-major float32.  X is [n_patterns x n_features], the
+ *    targets t are [n_patterns].
+ *  - Gene layout (canonical, K = B*N*d + 1 genes): gene 0 is the bias a_0;
+ *    gene 1 + i*B*d + b*d + (j-1) multiplies phi_{b,j}(f_i) for feature i
+ *    (0-based), block b (B = 2 only for GAME_TRIG: b = 0 cos(jx), b = 1
+ *    sin(jx)) and degree j = 1..d.  A population is [P x K] row-major.
+ *  - A handle is used by one host thread at a time; calls on one handle
+ *    are ordered by its stream.
+ */
+#ifndef GAME_H
+#define GAME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct game_ctx* game_t;
+
+typedef enum {
+  GAME_OK = 0,
+  GAME_EINVAL = -1,     /* an argument or the configuration is invalid     */
+  GAME_EWORKSPACE = -2, /* the workspace is missing, too small or unaligned */
+  GAME_EHIP = -3,       /* a HIP runtime call failed                        */
+  GAME_ESTATE = -4      /* the call is not valid in the handle's state      */
+} game_status;
+
+/* Expansion families: Eq. 1 leaves g(x) free; Eq. 8 is the trigonometric
+ * one the paper uses.  Chebyshev T_j, Legendre P_j, powers x^j, cos/sin(jx). */
+typedef enum { GAME_CHEBYSHEV = 0, GAME_LEGENDRE = 1, GAME_POWER = 2, GAME_TRIG = 3 } game_basis;
+
+/* Error functions: MSE (Eq. 4), RMSE (Eq. 5), TMSE (Eq. 10).  TMSE counts
+ * a pattern's squared residual only when |t - Out| > R (the reading under
+ * which the paper's worked example holds); GAME_TMSE_SQUARED compares the
+ * squared residual with R as Eq. 10 is printed. */
+typedef enum { GAME_MSE = 0, GAME_RMSE = 1, GAME_TMSE = 2, GAME_TMSE_SQUARED = 3 } game_error_fn;
+
+typedef enum { GAME_FP32 = 0, GAME_BF16 = 1 } game_precision;
+
+/* Initial population (the three random modes listed in Sec. 2): normal in
+ * [-1, 1] (sigma 1/3, clamped), uniform in [-1, 1), uniform in [0, 1). */
+typedef enum { GAME_INIT_NORMAL = 0, GAME_INIT_UNIFORM = 1, GAME_INIT_UNIT = 2 } game_init;
+
+/* Run configuration (the user options of Sec. 2 and the parameters of
+ * Sec. 5).  Genetic operators: tournament selection of size tournament_k
+ * with replacement (lowest (fitness, index) wins); one-point crossover with
+ * probability p_crossover and cut in [1, K-1]; per-gene Gaussian mutation
+ * g <- clamp(g + sigma_mutation * z, -1, 1) with probability p_mutation;
+ * elitism keeps `elitism` chromosomes unchanged (elite_mode 0: that many
+ * copies of the winner, as the paper words it; 1: the best `elitism`).
+ * Every random draw is Philox4x64-10 keyed by (seed, stream) with counter
+ * (generation, unit, block, 0). */
+typedef struct {
+  int32_t basis;          /* game_basis                                   */
+  int32_t degree;         /* d, 1..16                                     */
+  int32_t population;     /* P, 2..8192                                   */
+  int32_t tournament_k;   /* 1..population (paper: 4)                     */
+  int32_t elitism;        /* 0..population-1 (paper: 2)                   */
+  int32_t elite_mode;     /* 0 or 1                                       */
+  int32_t init_mode;      /* game_init                                    */
+  int32_t error_fn;       /* game_error_fn                                */
+  int32_t precision;      /* game_precision                               */
+  float p_crossover;      /* [0, 1] (paper: 0.9)                          */
+  float p_mutation;       /* [0, 1] (paper: 0.2)                          */
+  float sigma_mutation;   /* >= 0                                         */
+  float tmse_R;           /* TMSE threshold R in (0, 1) (paper: 0.49)     */
+  uint64_t seed;
+  int32_t max_generations;/* stop after this many evolution steps        */
+  double target;          /* stop when the best error <= target (0.001)  */
+} game_config;
+
+/* Fills *cfg with the defaults: Chebyshev, d = 4, P = 50, k = 3, elitism 2
+ * (mode 0), normal init, MSE, FP32, p_c 0.9, p_m 0.05, sigma 0.1, R 0.49,
+ * seed 0, 100 generations, target 0.001.  Returns GAME_EINVAL on NULL. */
+int game_config_default(game_config* cfg);
+
+/* K = B*N*d + 1 for this configuration and feature count (Eq. 2 with
+ * per-feature genes), or GAME_EINVAL. */
+int game_num_genes(const game_config* cfg, int32_t n_features);
+
+/* Bytes of device workspace game_create needs for this problem; 0 when the
+ * configuration is invalid (see game_last_error()). */
+size_t game_workspace_size(const game_config* cfg, int64_t n_patterns, int32_t n_features);
+
+/* Creates a handle over a resident data set (the patterns of Sec. 2).
+ * X_dev, t_dev and workspace_dev must stay valid and X_dev/t_dev unchanged
+ * until game_destroy.  workspace_dev must be 256-byte aligned and at least
+ * game_workspace_size() bytes.  Validates the configuration (GAME_EINVAL),
+ * the workspace (GAME_EWORKSPACE).  The population is not initialised. */
+int game_create(const game_config* cfg, const float* X_dev, const float* t_dev,
+                int64_t n_patterns, int32_t n_features, void* workspace_dev,
+                size_t workspace_bytes, void* hip_stream, game_t* out);
+
+int game_destroy(game_t h);
+
+/* Fitness of n chromosomes genes_dev [n x K] over the handle's data set
+ * with the handle's error function (Eqs. 2-5, 10): fitness_dev [n] float32
+ * and, if fitness64_dev is not NULL, the same values as float64.  Sums are
+ * accumulated in float64 in a fixed order (deterministic).  A chromosome
+ * whose error is NaN gets +inf.  1 <= n <= population. */
+int game_fitness(game_t h, const float* genes_dev, int32_t n, float* fitness_dev,
+                 double* fitness64_dev);
+
+/* Error of n chromosomes on another data set of the same feature count
+ * (the "test" use case of Sec. 2): err64_dev [n] float64.  X_dev/t_dev as
+ * in game_create; 1 <= n <= population. */
+int game_evaluate(game_t h, const float* X_dev, const float* t_dev, int64_t n_patterns,
+                  const float* genes_dev, int32_t n, double* err64_dev);
+
+/* Generation 0: random genes per cfg.init_mode (stream 0, unit =
+ * chromosome, block = gene).  Resets the generation counter and stop flag. */
+int game_init_population(game_t h);
+
+/* One iteration of the loop of Sec. 4.1 on the stream: evaluate the
+ * current population, rank it, test the stop criteria (best error <=
+ * cfg.target or generation >= cfg.max_generations) and, unless stopped,
+ * build the next generation.  Once stopped, further steps do nothing. */
+int game_step(game_t h);
+
+/* Runs steps until a stop criterion holds, with the loop captured in a HIP
+ * graph (no host round trip per generation); synchronises the stream.
+ * max_generations < 0 and target < 0 keep the configured values.  Outputs
+ * (each may be NULL): the number of evolution steps applied since the
+ * last init/set, the best chromosome [K] and its float64 error. */
+int game_run(game_t h, int32_t max_generations, double target, int32_t* generations_done,
+             float* best_genes_host, double* best_error_host);
+
+/* Current population [P x K] and, if fitness_dev is not NULL, its fitness
+ * [P] as last evaluated (copies on the stream). */
+int game_get_population(game_t h, float* genes_dev, float* fitness_dev);
+
+/* Replaces the current population (resume from a stored population, the
+ * "train" use case's output) and sets the generation counter. */
+int game_set_population(game_t h, const float* genes_dev, int32_t generation);
+
+/* Synchronises the stream and reports the generation counter, the stop
+ * flag, the best index of the last evaluation and its float64 error. */
+int game_get_state(game_t h, int32_t* generation, int32_t* stopped, int32_t* best_index,
+                   double* best_error);
+
+/* Rank order of n fitness values (the "sort the best chromosomes" step of
+ * Sec. 4.1): order_dev[r] is the index of rank r by (fitness ascending,
+ * index ascending), NaN counted as +inf and -0 as +0.  1 <= n <= 8192. */
+int game_rank(const float* fitness_dev, int32_t n, int32_t* order_dev, void* hip_stream);
+
+/* Stateless genetic step: builds generation `generation` (>= 1) in
+ * out_dev [P x K] from pop_dev [P x K] and its float32 fitness_dev [P],
+ * with cfg's operators and seed (elitism, tournament, one-point crossover,
+ * Gaussian mutation).  Bit-exact for given inputs.  workspace_dev: at least
+ * game_ga_workspace_size(cfg) bytes, 256-byte aligned.  out_dev must not
+ * overlap pop_dev. */
+size_t game_ga_workspace_size(const game_config* cfg);
+int game_ga_next(const game_config* cfg, int32_t n_genes, const float* pop_dev,
+                 const float* fitness_dev, int32_t generation, float* out_dev,
+                 void* workspace_dev, size_t workspace_bytes, void* hip_stream);
+
+/* Stateless generation-0 population [P x n_genes] (cfg.init_mode, cfg.seed). */
+int game_init_genes(const game_config* cfg, int32_t n_genes, float* out_dev, void* hip_stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* game_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAME_H */

@@ -1,0 +1,339 @@
+// Fused GAME fitness in float32 on MFMA (gfx950).
+//
+// For chromosome p and pattern k (Eq. 2 with per-feature genes):
+//   Out[k,p] = a_0(p) + sum_{i,b,j} gene_p(i,b,j) * phi_{b,j}(x_{k,i})
+// and the fitness is sum_k E_k / NP with E_k = (t_k - Out[k,p])^2 (Eqs. 3-4)
+// or its thresholded form (Eq. 10).  The sum over (i,b,j) is a dense
+// contraction: M = patterns, N = chromosomes, K = B*N*d expansion terms.
+//
+// Design:
+//  * v_mfma_f32_32x32x2_f32.  The A operand (patterns x K) is never stored:
+//    each lane owns one pattern row and one sub-feature u = (i, b) and
+//    produces phi_1..phi_d of that sub-feature with the basis's three-term
+//    recurrence, one value per K-step.  K is ordered so that the two lane
+//    halves of a K-step carry sub-features 2q and 2q+1 at the same degree j,
+//    so a lane's recurrence never crosses a feature boundary.
+//  * The B operand (K x chromosomes) is staged once per workgroup in LDS in
+//    that permuted order (odd row stride: conflict-free ds_read_b32).  When
+//    K does not fit, it is staged in chunks of whole feature pairs.
+//  * Accumulators start at a_0(p) - t_k, so after the K loop they hold
+//    Out - t; the epilogue squares, applies the error function and sums the
+//    lane's 32 rows in float32, then adds into a float64 running sum.
+//    Partials per (chromosome, split) are combined in a fixed order: the
+//    result does not depend on scheduling.
+//  * Grid: (pattern split) x (64-chromosome tile); consecutive blocks of one
+//    split are mapped onto one XCD so its L2 serves the split's rows to all
+//    chromosome tiles.
+#include <utility>
+
+#include "common.h"
+
+namespace game {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+template <int BASIS>
+struct Recur;
+
+// Chebyshev: T_{j+1} = 2x T_j - T_{j-1}
+template <>
+struct Recur<0> {
+  float prev, cur, m2;
+  __device__ void seed(float x, int) { prev = 1.f; cur = x; m2 = 2.f * x; }
+  template <int J>
+  __device__ void advance(float) { float n = fmaf(m2, cur, -prev); prev = cur; cur = n; }
+};
+// Legendre: (j+1) P_{j+1} = (2j+1) x P_j - j P_{j-1}
+template <>
+struct Recur<1> {
+  float prev, cur;
+  __device__ void seed(float x, int) { prev = 1.f; cur = x; }
+  template <int J>
+  __device__ void advance(float x) {
+    constexpr float a = float(2 * J + 1) / float(J + 1);
+    constexpr float b = float(J) / float(J + 1);
+    float n = fmaf(a * x, cur, -b * prev);
+    prev = cur; cur = n;
+  }
+};
+// Powers: x^{j+1} = x * x^j
+template <>
+struct Recur<2> {
+  float cur;
+  __device__ void seed(float x, int) { cur = x; }
+  template <int J>
+  __device__ void advance(float x) { cur *= x; }
+};
+// Trigonometric (Eq. 8): cos/sin((j+1)x) = 2 cos x * cos/sin(jx) - cos/sin((j-1)x).
+// Lane half 0 runs the cos chain, half 1 the sin chain of the same feature.
+template <>
+struct Recur<3> {
+  float prev, cur, m2;
+  __device__ void seed(float x, int half) {
+    float s, c;
+    sincosf(x, &s, &c);
+    prev = half ? 0.f : 1.f;
+    cur = half ? s : c;
+    m2 = 2.f * c;
+  }
+  template <int J>
+  __device__ void advance(float) { float n = fmaf(m2, cur, -prev); prev = cur; cur = n; }
+};
+
+__device__ __forceinline__ float error_term(float v, int error_fn, float R) {
+  float e = v * v;
+  if (error_fn == 2) e = fabsf(v) > R ? e : 0.f;       // TMSE, |r| > R
+  else if (error_fn == 3) e = e > R ? e : 0.f;          // TMSE as printed
+  return e;
+}
+
+template <int BASIS, int D>
+__global__ __launch_bounds__(kFitThreads, 2) void fitness_f32_kernel(FitArgs a) {
+  extern __shared__ float lds[];
+  if (a.stop && *a.stop) return;
+  const float* __restrict__ genes = a.genes;
+  if (a.gen_sel && (*a.gen_sel & 1)) genes = a.genes_alt;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int m = lane & 31;
+  const int h = lane >> 5;
+
+  const int total = gridDim.x;
+  const int b = blockIdx.x;
+  const int L = a.xcd_remap ? (b & 7) * (total >> 3) + (b >> 3) : b;
+  const int split = L / a.n_ctiles;
+  const int ctile = L - split * a.n_ctiles;
+  const int c0 = ctile * kTileCols;
+
+  const int ppc = a.pairs_per_chunk;
+  const int SC = ppc * D;          // K-steps per chunk
+  const int WS = 2 * SC + 1;       // LDS row stride in floats (odd)
+  const int K = a.K;
+
+  float w0[2];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const int n = c0 + cb * 32 + m;
+    w0[cb] = n < a.n_chrom ? genes[(int64_t)n * K] : 0.f;
+  }
+
+  // Stage the genes of feature pairs [chunk*ppc, chunk*ppc + ppc) of this
+  // chromosome tile: lds[c*WS + half*SC + qq*D + (j-1)].
+  auto stage = [&](int chunk) {
+    const int g0 = chunk * ppc * 2 * D;       // first expansion gene of the chunk
+    const int span = 2 * SC;
+    for (int idx = threadIdx.x; idx < kTileCols * span; idx += kFitThreads) {
+      const int c = idx / span;
+      const int g = idx - c * span;           // offset within the chunk
+      const int u_off = g / D;
+      const int j = g - u_off * D;
+      const int u = chunk * ppc * 2 + u_off;
+      const int n = c0 + c;
+      float v = 0.f;
+      if (n < a.n_chrom && u < a.U) v = genes[(int64_t)n * K + 1 + g0 + g];
+      lds[c * WS + (u_off & 1) * SC + (u_off >> 1) * D + j] = v;
+    }
+  };
+
+  if (a.n_chunks == 1) {
+    stage(0);
+    __syncthreads();
+  }
+
+  double acc64[2] = {0.0, 0.0};
+  const int64_t NP = a.NP;
+  const int N = a.N;
+  const int tile_begin = split * a.tiles_per_split;
+  const int tile_end = min(tile_begin + a.tiles_per_split, a.n_tiles);
+
+  for (int tile = tile_begin; tile < tile_end; ++tile) {
+    const int64_t row0 = (int64_t)tile * kTileRows + wave * 64;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        int64_t row = row0 + rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+        row = row < NP ? row : NP - 1;
+        const float tv = a.t[row];
+        acc[rb][0][i] = w0[0] - tv;
+        acc[rb][1][i] = w0[1] - tv;
+      }
+    }
+    // rows this lane feeds into the A operand
+    int64_t arow[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      const int64_t r = row0 + rb * 32 + m;
+      arow[rb] = r < NP ? r : -1;
+    }
+
+    for (int chunk = 0; chunk < a.n_chunks; ++chunk) {
+      if (a.n_chunks > 1) {
+        __syncthreads();
+        stage(chunk);
+        __syncthreads();
+      }
+      const int q_begin = chunk * ppc;
+      const int q_end = min(q_begin + ppc, a.Q);
+      for (int q = q_begin; q < q_end; ++q) {
+        // feature of this lane: trig pairs are (cos, sin) of feature q,
+        // the other bases pair features 2q and 2q+1
+        const int u = 2 * q + h;
+        const int f = BASIS == 3 ? q : u;
+        const bool fvalid = BASIS == 3 ? true : (u < a.U);
+        Recur<BASIS> rc[2];
+        float x[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          x[rb] = (arow[rb] >= 0 && fvalid) ? a.X[arow[rb] * N + f] : 0.f;
+          rc[rb].seed(x[rb], h);
+        }
+        const float* wl = lds + m * WS + h * SC + (q - q_begin) * D;
+        // One K-step per degree: two MFMA columns x two row blocks, then the
+        // recurrence moves every lane's A value to the next degree.
+        auto kstep = [&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          const float b0 = wl[j];
+          const float b1 = wl[32 * WS + j];
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb) {
+            acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(rc[rb].cur, b0, acc[rb][0], 0, 0, 0);
+            acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(rc[rb].cur, b1, acc[rb][1], 0, 0, 0);
+          }
+          if constexpr (j + 1 < D) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) rc[rb].template advance<j + 1>(x[rb]);
+          }
+        };
+        [&]<int... J>(std::integer_sequence<int, J...>) {
+          (kstep(std::integral_constant<int, J>{}), ...);
+        }(std::make_integer_sequence<int, D>{});
+      }
+    }
+
+    // Epilogue: squared (or thresholded) residuals of the lane's rows.
+    const bool full = row0 + 64 <= NP;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      float s = 0.f;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          float e = error_term(acc[rb][cb][i], a.error_fn, a.R);
+          if (!full) {
+            const int64_t row = row0 + rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+            e = row < NP ? e : 0.f;
+          }
+          s += e;
+        }
+      }
+      acc64[cb] += (double)s;
+    }
+  }
+
+  // Combine the two lane halves (same chromosome, different rows), then the
+  // four waves, in a fixed order.
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) acc64[cb] += __shfl_xor(acc64[cb], 32);
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(lds);
+  if (h == 0) {
+    red[wave * 64 + m] = acc64[0];
+    red[wave * 64 + 32 + m] = acc64[1];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int c = threadIdx.x;
+    const double v = ((red[c] + red[64 + c]) + red[128 + c]) + red[192 + c];
+    a.partial[(int64_t)(c0 + c) * a.n_splits + split] = v;
+  }
+}
+
+template <int BASIS, int D>
+static hipError_t launch_one(const FitArgs& a, hipStream_t s) {
+  const size_t lds = fitness_lds_bytes(a, D);
+  const int grid = a.n_ctiles * a.n_splits;
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)fitness_f32_kernel<BASIS, D>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((fitness_f32_kernel<BASIS, D>), dim3(grid), dim3(kFitThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int BASIS>
+static hipError_t launch_basis(const FitArgs& a, int degree, hipStream_t s) {
+  switch (degree) {
+#define GAME_CASE(D) case D: return launch_one<BASIS, D>(a, s);
+    GAME_CASE(1) GAME_CASE(2) GAME_CASE(3) GAME_CASE(4) GAME_CASE(5) GAME_CASE(6)
+    GAME_CASE(7) GAME_CASE(8) GAME_CASE(9) GAME_CASE(10) GAME_CASE(11) GAME_CASE(12)
+    GAME_CASE(13) GAME_CASE(14) GAME_CASE(15) GAME_CASE(16)
+#undef GAME_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fitness_f32(const FitArgs& a, int basis, int degree, hipStream_t s) {
+  switch (basis) {
+    case 0: return launch_basis<0>(a, degree, s);
+    case 1: return launch_basis<1>(a, degree, s);
+    case 2: return launch_basis<2>(a, degree, s);
+    case 3: return launch_basis<3>(a, degree, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t fitness_lds_bytes(const FitArgs& a, int degree) {
+  const size_t w = (size_t)kTileCols * (2 * a.pairs_per_chunk * degree + 1) * sizeof(float);
+  const size_t red = 4 * 64 * sizeof(double);
+  return w > red ? w : red;
+}
+
+void plan_fitness(FitArgs& a, int degree, int basis) {
+  a.U = (basis == 3 ? 2 : 1) * a.N;
+  a.Q = (a.U + 1) / 2;
+  int ppc = kMaxChunkSteps / degree;
+  if (ppc < 1) ppc = 1;
+  if (ppc > a.Q) ppc = a.Q;
+  a.pairs_per_chunk = ppc;
+  a.n_chunks = (a.Q + ppc - 1) / ppc;
+  a.n_ctiles = (a.n_chrom + kTileCols - 1) / kTileCols;
+  a.n_tiles = (int32_t)((a.NP + kTileRows - 1) / kTileRows);
+  // Aim at two resident workgroups per CU on 256 CUs in one wave of blocks.
+  const int target = 512;
+  int splits = (target + a.n_ctiles - 1) / a.n_ctiles;
+  if (splits > kMaxSplits) splits = kMaxSplits;
+  if (splits > a.n_tiles) splits = a.n_tiles;
+  if (splits < 1) splits = 1;
+  a.tiles_per_split = (a.n_tiles + splits - 1) / splits;
+  a.n_splits = (a.n_tiles + a.tiles_per_split - 1) / a.tiles_per_split;
+  a.xcd_remap = ((a.n_ctiles * a.n_splits) % 8) == 0 ? 1 : 0;
+}
+
+// fitness[i] = sum_s partial[i][s] / NP (fixed order), RMSE takes the root;
+// NaN becomes +inf.
+__global__ void finish_kernel(const double* __restrict__ partial, int32_t n, int32_t n_splits,
+                              int64_t NP, int32_t error_fn, float* f32, double* f64) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < n_splits; ++k) s += partial[(int64_t)i * n_splits + k];
+  double v = s / (double)NP;
+  if (error_fn == 1) v = sqrt(v);
+  if (isnan(v)) v = INFINITY;
+  if (f32) f32[i] = (float)v;
+  if (f64) f64[i] = v;
+}
+
+hipError_t launch_finish(const double* partial, int32_t n, int32_t n_splits, int64_t NP,
+                         int32_t error_fn, float* f32, double* f64, hipStream_t s) {
+  hipLaunchKernelGGL(finish_kernel, dim3((n + 255) / 256), dim3(256), 0, s, partial, n, n_splits,
+                     NP, error_fn, f32, f64);
+  return hipGetLastError();
+}
+
+}  // namespace game

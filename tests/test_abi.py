@@ -1,0 +1,107 @@
+"""The C-ABI library loads, exports every function include/game.h declares,
+lays out game_config as C does, and validates configurations (host logic,
+no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1304_0597_amd import game
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "game.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(game_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for n in ["game_create", "game_fitness", "game_step", "game_run", "game_destroy",
+              "game_ga_next", "game_rank", "game_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = game.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(declared_functions()) <= set(game._SIGS), "binding lacks a signature"
+
+
+def test_config_struct_layout_matches_c(tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "game.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu\", sizeof(game_config),"
+        " offsetof(game_config, p_crossover), offsetof(game_config, seed),"
+        " offsetof(game_config, max_generations), offsetof(game_config, target));return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    g = game.game_config
+    assert got == [ctypes.sizeof(g), g.p_crossover.offset, g.seed.offset,
+                   g.max_generations.offset, g.target.offset]
+
+
+def test_defaults_and_gene_counts():
+    c = game.config()
+    assert (c.basis, c.degree, c.population, c.tournament_k, c.elitism) == (0, 4, 50, 3, 2)
+    assert abs(c.p_crossover - 0.9) < 1e-7 and abs(c.target - 1e-3) < 1e-15
+    assert game.game_num_genes(c, 7) == 29
+    assert game.game_num_genes(game.config(basis=game.GAME_LEGENDRE, degree=8), 20) == 161
+    assert game.game_num_genes(game.config(basis=game.GAME_TRIG, degree=8), 11) == 177
+
+
+@pytest.mark.parametrize("field,value", [
+    ("basis", 4), ("degree", 0), ("degree", 17), ("population", 1), ("population", 8193),
+    ("tournament_k", 0), ("tournament_k", 65), ("elitism", 50), ("elite_mode", 2),
+    ("init_mode", 3), ("error_fn", 4), ("p_crossover", 1.5), ("p_mutation", -0.1),
+    ("sigma_mutation", -1.0), ("max_generations", -1),
+])
+def test_invalid_configs_are_rejected(field, value):
+    c = game.config()
+    setattr(c, field, value)
+    with pytest.raises(game.GameError) as ei:
+        game.game_num_genes(c, 7)
+    assert ei.value.code == game.GAME_EINVAL
+    assert game.game_last_error()
+    assert game.lib().game_workspace_size(ctypes.byref(c), 100, 7) == 0
+
+
+def test_tmse_threshold_range():
+    c = game.config(error_fn=game.GAME_TMSE, tmse_R=0.0)
+    with pytest.raises(game.GameError):
+        game.game_num_genes(c, 3)
+    c.tmse_R = 0.49
+    assert game.game_num_genes(c, 3) == 13
+
+
+def test_too_many_genes():
+    c = game.config(degree=16)
+    assert game.game_num_genes(c, 256) == 4097
+    with pytest.raises(game.GameError):
+        game.game_num_genes(c, 257)
+
+
+def test_workspace_size_grows_with_population():
+    a = game.game_workspace_size(game.config(population=64), 1000, 8)
+    b = game.game_workspace_size(game.config(population=2048), 1000, 8)
+    assert b > a > 0 and a % 256 == 0 and b % 256 == 0
+
+
+def test_null_arguments_fail_without_gpu():
+    L = game.lib()
+    assert L.game_destroy(None) == game.GAME_EINVAL
+    h = ctypes.c_void_p()
+    c = game.config()
+    rc = L.game_create(ctypes.byref(c), None, None, 10, 7, None, 0, None, ctypes.byref(h))
+    assert rc == game.GAME_EINVAL and h.value is None
+    assert L.game_config_default(None) == game.GAME_EINVAL
