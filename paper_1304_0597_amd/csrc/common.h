@@ -31,7 +31,8 @@ struct RunState {
   double best_err;      // float64 error of `best`
   double target;        // stop when best_err <= target
   int32_t evaluated;    // generation of the last evaluation, -1 if none
-  int32_t pad[7];
+  int32_t stop_seen;    // stop flag as the generation's fitness launch saw it
+  int32_t pad[6];
 };
 
 // Problem view for the fitness kernels.
@@ -42,7 +43,8 @@ struct FitArgs {
   const float* genes_alt;   // second buffer of a ping-pong pair (or null)
   const int32_t* gen_sel;   // when set, genes_alt is used if (*gen_sel & 1)
   const int32_t* stop;      // when set and nonzero the kernel returns
-  double* partial;          // [n_ctiles*64 x n_splits] float64 SSE partials
+  int32_t* stop_seen;       // when set, block 0 records *stop here
+  double* partial;          // [n_splits x ld_partial] float64 SSE partials
   int64_t NP;
   int32_t N;
   int32_t K;
@@ -52,6 +54,7 @@ struct FitArgs {
   int32_t pairs_per_chunk;
   int32_t n_chunks;
   int32_t n_ctiles;
+  int32_t ld_partial;       // n_ctiles * 64
   int32_t n_splits;
   int32_t tiles_per_split;
   int32_t n_tiles;
@@ -65,7 +68,7 @@ void plan_fitness(FitArgs& a, int degree, int basis);
 size_t fitness_lds_bytes(const FitArgs& a, int degree);
 
 hipError_t launch_fitness_f32(const FitArgs& a, int basis, int degree, hipStream_t s);
-hipError_t launch_finish(const double* partial, int32_t n, int32_t n_splits, int64_t NP,
+hipError_t launch_finish(const double* partial, int32_t ld, int32_t n, int32_t n_splits, int64_t NP,
                          int32_t error_fn, float* f32, double* f64, hipStream_t s);
 hipError_t launch_init_genes(uint64_t seed, int32_t mode, int32_t P, int32_t K, float* out,
                              hipStream_t s);
@@ -94,8 +97,10 @@ struct GAArgs {
 hipError_t launch_ga_next(const GAArgs& a, hipStream_t s);
 
 // Evaluation epilogue of a run: float64 errors, rank, best, stop test.
+// Grid: ceil(P / kRankPerBlock) workgroups of kRankThreads.
 struct RankArgs {
   const double* partial;
+  int32_t ld_partial;
   int32_t n_splits;
   int64_t NP;
   int32_t P;
@@ -106,6 +111,8 @@ struct RankArgs {
   RunState* state;
 };
 hipError_t launch_finish_rank(const RankArgs& a, hipStream_t s);
+constexpr int kRankThreads = 1024;
+constexpr int kRankPerBlock = 64;
 hipError_t launch_set_state(RunState* st, int32_t gen, int32_t max_gen, double target,
                             int32_t reset, hipStream_t s);
 

@@ -80,17 +80,24 @@ struct Recur<3> {
   __device__ void advance(float) { float n = fmaf(m2, cur, -prev); prev = cur; cur = n; }
 };
 
-__device__ __forceinline__ float error_term(float v, int error_fn, float R) {
-  float e = v * v;
-  if (error_fn == 2) e = fabsf(v) > R ? e : 0.f;       // TMSE, |r| > R
-  else if (error_fn == 3) e = e > R ? e : 0.f;          // TMSE as printed
+// Squared residual (MSE, RMSE) or its thresholded form (TMSE, Eq. 10):
+// mode 2 keeps it when |r| > R, mode 3 when r^2 > R.
+template <int MODE>
+__device__ __forceinline__ float error_term(float v, float R) {
+  const float e = v * v;
+  if constexpr (MODE == 2) return fabsf(v) > R ? e : 0.f;
+  if constexpr (MODE == 3) return e > R ? e : 0.f;
   return e;
 }
 
 template <int BASIS, int D>
 __global__ __launch_bounds__(kFitThreads, 2) void fitness_f32_kernel(FitArgs a) {
   extern __shared__ float lds[];
-  if (a.stop && *a.stop) return;
+  if (a.stop) {
+    const int32_t stopped = *a.stop;
+    if (a.stop_seen && blockIdx.x == 0 && threadIdx.x == 0) *a.stop_seen = stopped;
+    if (stopped) return;
+  }
   const float* __restrict__ genes = a.genes;
   if (a.gen_sel && (*a.gen_sel & 1)) genes = a.genes_alt;
 
@@ -147,26 +154,33 @@ __global__ __launch_bounds__(kFitThreads, 2) void fitness_f32_kernel(FitArgs a) 
   const int tile_begin = split * a.tiles_per_split;
   const int tile_end = min(tile_begin + a.tiles_per_split, a.n_tiles);
 
-  for (int tile = tile_begin; tile < tile_end; ++tile) {
-    const int64_t row0 = (int64_t)tile * kTileRows + wave * 64;
-    f32x16 acc[2][2];
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        int64_t row = row0 + rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-        row = row < NP ? row : NP - 1;
-        const float tv = a.t[row];
-        acc[rb][0][i] = w0[0] - tv;
-        acc[rb][1][i] = w0[1] - tv;
-      }
-    }
-    // rows this lane feeds into the A operand
-    int64_t arow[2];
+  // x of sub-feature pair q for this lane's two rows (0 outside the data).
+  auto load_x = [&](int64_t row0, int q, float (&xo)[2]) {
+    const int u = 2 * q + h;
+    const int f = BASIS == 3 ? q : u;
+    const bool fvalid = BASIS == 3 ? true : (u < a.U);
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
       const int64_t r = row0 + rb * 32 + m;
-      arow[rb] = r < NP ? r : -1;
+      xo[rb] = (r < NP && fvalid) ? a.X[r * N + f] : 0.f;
+    }
+  };
+
+  float xn[2] = {0.f, 0.f};
+  if (tile_begin < tile_end) load_x((int64_t)tile_begin * kTileRows + wave * 64, 0, xn);
+
+  for (int tile = tile_begin; tile < tile_end; ++tile) {
+    const int64_t row0 = (int64_t)tile * kTileRows + wave * 64;
+    // One target per lane (the wave's 64 rows); the epilogue redistributes
+    // them across lanes, so the load's latency hides behind the K loop.
+    const float t_lane = a.t[row0 + lane < NP ? row0 + lane : NP - 1];
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      acc[0][0][i] = w0[0];
+      acc[0][1][i] = w0[1];
+      acc[1][0][i] = w0[0];
+      acc[1][1][i] = w0[1];
     }
 
     for (int chunk = 0; chunk < a.n_chunks; ++chunk) {
@@ -178,18 +192,13 @@ __global__ __launch_bounds__(kFitThreads, 2) void fitness_f32_kernel(FitArgs a) 
       const int q_begin = chunk * ppc;
       const int q_end = min(q_begin + ppc, a.Q);
       for (int q = q_begin; q < q_end; ++q) {
-        // feature of this lane: trig pairs are (cos, sin) of feature q,
-        // the other bases pair features 2q and 2q+1
-        const int u = 2 * q + h;
-        const int f = BASIS == 3 ? q : u;
-        const bool fvalid = BASIS == 3 ? true : (u < a.U);
+        float x[2] = {xn[0], xn[1]};
+        // prefetch the next pair, or the first pair of the next tile
+        if (q + 1 < a.Q) load_x(row0, q + 1, xn);
+        else if (tile + 1 < tile_end) load_x(row0 + kTileRows, 0, xn);
         Recur<BASIS> rc[2];
-        float x[2];
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
-          x[rb] = (arow[rb] >= 0 && fvalid) ? a.X[arow[rb] * N + f] : 0.f;
-          rc[rb].seed(x[rb], h);
-        }
+        for (int rb = 0; rb < 2; ++rb) rc[rb].seed(x[rb], h);
         const float* wl = lds + m * WS + h * SC + (q - q_begin) * D;
         // One K-step per degree: two MFMA columns x two row blocks, then the
         // recurrence moves every lane's A value to the next degree.
@@ -213,25 +222,36 @@ __global__ __launch_bounds__(kFitThreads, 2) void fitness_f32_kernel(FitArgs a) 
       }
     }
 
-    // Epilogue: squared (or thresholded) residuals of the lane's rows.
+    // Epilogue: residual Out - t, squared (or thresholded), summed over the
+    // lane's 32 rows.  Accumulator register i of row block rb holds row
+    // rb*32 + 8*(i/4) + 4*h + i%4 of the wave's 64 rows.
     const bool full = row0 + 64 <= NP;
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      float s = 0.f;
+    float s[2] = {0.f, 0.f};
+    auto epilogue = [&](auto mode_c) {
+      constexpr int mode = decltype(mode_c)::value;
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-          float e = error_term(acc[rb][cb][i], a.error_fn, a.R);
+          const int rl = rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+          const float tv = __shfl(t_lane, rl);
+          float e0 = error_term<mode>(acc[rb][0][i] - tv, a.R);
+          float e1 = error_term<mode>(acc[rb][1][i] - tv, a.R);
           if (!full) {
-            const int64_t row = row0 + rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-            e = row < NP ? e : 0.f;
+            const bool ok = row0 + rl < NP;
+            e0 = ok ? e0 : 0.f;
+            e1 = ok ? e1 : 0.f;
           }
-          s += e;
+          s[0] += e0;
+          s[1] += e1;
         }
       }
-      acc64[cb] += (double)s;
-    }
+    };
+    if (a.error_fn == 2) epilogue(std::integral_constant<int, 2>{});
+    else if (a.error_fn == 3) epilogue(std::integral_constant<int, 3>{});
+    else epilogue(std::integral_constant<int, 0>{});
+    acc64[0] += (double)s[0];
+    acc64[1] += (double)s[1];
   }
 
   // Combine the two lane halves (same chromosome, different rows), then the
@@ -248,7 +268,7 @@ __global__ __launch_bounds__(kFitThreads, 2) void fitness_f32_kernel(FitArgs a) 
   if (threadIdx.x < 64) {
     const int c = threadIdx.x;
     const double v = ((red[c] + red[64 + c]) + red[128 + c]) + red[192 + c];
-    a.partial[(int64_t)(c0 + c) * a.n_splits + split] = v;
+    a.partial[(int64_t)split * a.ld_partial + c0 + c] = v;
   }
 }
 
@@ -302,6 +322,7 @@ void plan_fitness(FitArgs& a, int degree, int basis) {
   a.pairs_per_chunk = ppc;
   a.n_chunks = (a.Q + ppc - 1) / ppc;
   a.n_ctiles = (a.n_chrom + kTileCols - 1) / kTileCols;
+  a.ld_partial = a.n_ctiles * kTileCols;
   a.n_tiles = (int32_t)((a.NP + kTileRows - 1) / kTileRows);
   // Aim at two resident workgroups per CU on 256 CUs in one wave of blocks.
   const int target = 512;
@@ -314,14 +335,15 @@ void plan_fitness(FitArgs& a, int degree, int basis) {
   a.xcd_remap = ((a.n_ctiles * a.n_splits) % 8) == 0 ? 1 : 0;
 }
 
-// fitness[i] = sum_s partial[i][s] / NP (fixed order), RMSE takes the root;
+// fitness[i] = sum_s partial[s][i] / NP (fixed order), RMSE takes the root;
 // NaN becomes +inf.
-__global__ void finish_kernel(const double* __restrict__ partial, int32_t n, int32_t n_splits,
-                              int64_t NP, int32_t error_fn, float* f32, double* f64) {
+__global__ void finish_kernel(const double* __restrict__ partial, int32_t ld, int32_t n,
+                              int32_t n_splits, int64_t NP, int32_t error_fn, float* f32,
+                              double* f64) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
-  for (int k = 0; k < n_splits; ++k) s += partial[(int64_t)i * n_splits + k];
+  for (int k = 0; k < n_splits; ++k) s += partial[(int64_t)k * ld + i];
   double v = s / (double)NP;
   if (error_fn == 1) v = sqrt(v);
   if (isnan(v)) v = INFINITY;
@@ -329,10 +351,10 @@ __global__ void finish_kernel(const double* __restrict__ partial, int32_t n, int
   if (f64) f64[i] = v;
 }
 
-hipError_t launch_finish(const double* partial, int32_t n, int32_t n_splits, int64_t NP,
-                         int32_t error_fn, float* f32, double* f64, hipStream_t s) {
-  hipLaunchKernelGGL(finish_kernel, dim3((n + 255) / 256), dim3(256), 0, s, partial, n, n_splits,
-                     NP, error_fn, f32, f64);
+hipError_t launch_finish(const double* partial, int32_t ld, int32_t n, int32_t n_splits,
+                         int64_t NP, int32_t error_fn, float* f32, double* f64, hipStream_t s) {
+  hipLaunchKernelGGL(finish_kernel, dim3((n + 255) / 256), dim3(256), 0, s, partial, ld, n,
+                     n_splits, NP, error_fn, f32, f64);
   return hipGetLastError();
 }
 

@@ -104,91 +104,101 @@ hipError_t launch_init_genes(uint64_t seed, int32_t mode, int32_t P, int32_t K, 
 }
 
 // ------------------------------------------------------------------ rank
-// Bitonic sort of n2 (power of two) 64-bit keys in LDS by one workgroup.
-__device__ void bitonic_sort(uint64_t* keys, int n2) {
-  for (int k = 2; k <= n2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint64_t x = keys[i], y = keys[ixj];
-          const bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            keys[i] = y;
-            keys[ixj] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
+// Ranks by counting: the rank of key e is the number of keys below it (keys
+// are unique: fitness bits then index).  Each workgroup holds all keys in
+// LDS and ranks kRankPerBlock of them; its 16 waves each count over one
+// sixteenth of the keys, every lane of a wave reading the same key.
+__device__ __forceinline__ uint64_t rank_key(float f, int i) {
+  return ((uint64_t)ordered_bits(rank_key_value(f)) << 32) | (uint32_t)i;
 }
 
-__device__ __forceinline__ int pow2_at_least(int n) {
-  int p = 1;
-  while (p < n) p <<= 1;
-  return p;
-}
-
-__global__ __launch_bounds__(1024) void rank_kernel(const float* __restrict__ fit, int32_t n,
-                                                    int32_t* __restrict__ order) {
-  extern __shared__ uint64_t keys[];
-  const int n2 = pow2_at_least(n);
-  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-    keys[i] = i < n ? ((uint64_t)ordered_bits(rank_key_value(fit[i])) << 32) | (uint32_t)i
-                    : ~0ull;
+__device__ __forceinline__ int count_rank(const uint64_t* keys, int P, int e, uint32_t* cnt) {
+  constexpr int parts = kRankThreads / kRankPerBlock;
+  const int part = threadIdx.x / kRankPerBlock;
+  uint32_t c = 0;
+  if (e < P) {
+    const uint64_t ke = keys[e];
+    const int per = (P + parts - 1) / parts;
+    const int j0 = part * per;
+    const int j1 = min(j0 + per, P);
+    for (int j = j0; j < j1; ++j) c += keys[j] < ke ? 1u : 0u;
   }
+  cnt[threadIdx.x] = c;
   __syncthreads();
-  bitonic_sort(keys, n2);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) order[i] = (int32_t)(keys[i] & 0xFFFFFFFFu);
+  int r = -1;
+  if (threadIdx.x < kRankPerBlock && e < P) {
+    uint32_t t = 0;
+    for (int k = 0; k < parts; ++k) t += cnt[k * kRankPerBlock + threadIdx.x];
+    r = (int)t;
+  }
+  return r;
 }
 
-static size_t rank_lds(int n) {
-  int p = 1;
-  while (p < n) p <<= 1;
-  return (size_t)p * sizeof(uint64_t);
+__global__ __launch_bounds__(kRankThreads) void rank_kernel(const float* __restrict__ fit, int32_t n,
+                                                            int32_t* __restrict__ order) {
+  extern __shared__ uint64_t keys[];
+  __shared__ uint32_t cnt[kRankThreads];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) keys[i] = rank_key(fit[i], i);
+  __syncthreads();
+  const int e = blockIdx.x * kRankPerBlock + (threadIdx.x % kRankPerBlock);
+  const int r = count_rank(keys, n, e, cnt);
+  if (r >= 0) order[r] = e;
+}
+
+// Allows more than 64 KiB of LDS per workgroup (gfx950 has 160 KiB per CU).
+static hipError_t allow_lds(const void* fn, size_t dynamic_bytes) {
+  if (dynamic_bytes + kRankThreads * sizeof(uint32_t) <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dynamic_bytes);
 }
 
 hipError_t launch_rank(const float* fit, int32_t n, int32_t* order, hipStream_t s) {
-  hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(1024), rank_lds(n), s, fit, n, order);
+  const hipError_t e = allow_lds((const void*)rank_kernel, (size_t)n * sizeof(uint64_t));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rank_kernel, dim3((n + kRankPerBlock - 1) / kRankPerBlock), dim3(kRankThreads),
+                     (size_t)n * sizeof(uint64_t), s, fit, n, order);
   return hipGetLastError();
 }
 
-// Evaluation epilogue of one generation: errors from the float64 partials,
-// rank order, best chromosome, stop test, and the generation counter.
-__global__ __launch_bounds__(1024) void finish_rank_kernel(RankArgs a) {
+__device__ __forceinline__ double error_of(const RankArgs& a, int i) {
+  double s = 0.0;
+  for (int k = 0; k < a.n_splits; ++k) s += a.partial[(int64_t)k * a.ld_partial + i];
+  double v = s / (double)a.NP;
+  if (a.error_fn == 1) v = sqrt(v);
+  if (isnan(v)) v = INFINITY;
+  return v;
+}
+
+// Evaluation epilogue of one generation: errors from the float64 partials
+// (the same fixed-order sums in every workgroup), rank order, best
+// chromosome, stop test and the generation counter.  The stop flag that
+// decides whether this launch works is the one the generation's fitness
+// launch recorded, so a workgroup that sets the flag cannot make another
+// workgroup of the same launch skip its share.
+__global__ __launch_bounds__(kRankThreads) void finish_rank_kernel(RankArgs a) {
   extern __shared__ uint64_t keys[];
+  __shared__ uint32_t cnt[kRankThreads];
   RunState* st = a.state;
-  if (st->stop) return;
+  if (st->stop_seen) return;
   const int P = a.P;
-  const int n2 = pow2_at_least(P);
-  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-    uint64_t key = ~0ull;
-    if (i < P) {
-      double s = 0.0;
-      for (int k = 0; k < a.n_splits; ++k) s += a.partial[(int64_t)i * a.n_splits + k];
-      double v = s / (double)a.NP;
-      if (a.error_fn == 1) v = sqrt(v);
-      if (isnan(v)) v = INFINITY;
-      const float f = (float)v;
+  const int lo = blockIdx.x * kRankPerBlock;
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    const double v = error_of(a, i);
+    const float f = (float)v;
+    keys[i] = rank_key(f, i);
+    if (i >= lo && i < lo + kRankPerBlock) {
       a.fit32[i] = f;
       a.fit64[i] = v;
-      key = ((uint64_t)ordered_bits(rank_key_value(f)) << 32) | (uint32_t)i;
     }
-    keys[i] = key;
   }
   __syncthreads();
-  bitonic_sort(keys, n2);
-  for (int i = threadIdx.x; i < P; i += blockDim.x) a.order[i] = (int32_t)(keys[i] & 0xFFFFFFFFu);
-  if (threadIdx.x == 0) {
-    const int best = (int)(keys[0] & 0xFFFFFFFFu);
-    double s = 0.0;
-    for (int k = 0; k < a.n_splits; ++k) s += a.partial[(int64_t)best * a.n_splits + k];
-    double v = s / (double)a.NP;
-    if (a.error_fn == 1) v = sqrt(v);
-    if (isnan(v)) v = INFINITY;
+  const int e = lo + (threadIdx.x % kRankPerBlock);
+  const int r = count_rank(keys, P, e, cnt);
+  if (r < 0) return;
+  a.order[r] = e;
+  if (r == 0) {
+    const double v = error_of(a, e);
     const int gen = st->gen;
-    st->best = best;
+    st->best = e;
     st->best_err = v;
     st->evaluated = gen;
     if (v <= st->target || gen >= st->max_gen) {
@@ -200,7 +210,10 @@ __global__ __launch_bounds__(1024) void finish_rank_kernel(RankArgs a) {
 }
 
 hipError_t launch_finish_rank(const RankArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(finish_rank_kernel, dim3(1), dim3(1024), rank_lds(a.P), s, a);
+  const hipError_t e = allow_lds((const void*)finish_rank_kernel, (size_t)a.P * sizeof(uint64_t));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(finish_rank_kernel, dim3((a.P + kRankPerBlock - 1) / kRankPerBlock),
+                     dim3(kRankThreads), (size_t)a.P * sizeof(uint64_t), s, a);
   return hipGetLastError();
 }
 
@@ -210,6 +223,7 @@ __global__ void set_state_kernel(RunState* st, int32_t gen, int32_t max_gen, dou
   if (reset) {
     st->gen = gen;
     st->stop = 0;
+    st->stop_seen = 0;
     st->best = -1;
     st->best_err = INFINITY;
     st->evaluated = -1;

@@ -171,10 +171,12 @@ int enqueue_step(game_ctx* h, hipStream_t s) {
   fa.genes_alt = h->pop[1];
   fa.gen_sel = &h->state->gen;
   fa.stop = &h->state->stop;
+  fa.stop_seen = &h->state->stop_seen;
   GAME_HIP(launch_fitness_f32(fa, h->cfg.basis, h->cfg.degree, s));
   RankArgs ra{};
   ra.partial = h->partial;
   ra.n_splits = fa.n_splits;
+  ra.ld_partial = fa.ld_partial;
   ra.NP = h->NP;
   ra.P = h->cfg.population;
   ra.error_fn = h->cfg.error_fn;
@@ -306,7 +308,7 @@ int game_fitness(game_t h, const float* genes, int32_t n, float* f32, double* f6
     return fail(GAME_EINVAL, "n %d not in 1..population (%d)", n, h->cfg.population);
   FitArgs fa = fit_args(h, h->X, h->t, h->NP, genes, n);
   GAME_HIP(launch_fitness_f32(fa, h->cfg.basis, h->cfg.degree, h->stream));
-  GAME_HIP(launch_finish(h->partial, n, fa.n_splits, h->NP, h->cfg.error_fn, f32, f64, h->stream));
+  GAME_HIP(launch_finish(h->partial, fa.ld_partial, n, fa.n_splits, h->NP, h->cfg.error_fn, f32, f64, h->stream));
   return GAME_OK;
 }
 
@@ -321,7 +323,7 @@ int game_evaluate(game_t h, const float* X, const float* t, int64_t NP, const fl
     return fail(GAME_EINVAL, "n %d not in 1..population (%d)", n, h->cfg.population);
   FitArgs fa = fit_args(h, X, t, NP, genes, n);
   GAME_HIP(launch_fitness_f32(fa, h->cfg.basis, h->cfg.degree, h->stream));
-  GAME_HIP(launch_finish(h->partial, n, fa.n_splits, NP, h->cfg.error_fn, nullptr, err64,
+  GAME_HIP(launch_finish(h->partial, fa.ld_partial, n, fa.n_splits, NP, h->cfg.error_fn, nullptr, err64,
                          h->stream));
   return GAME_OK;
 }

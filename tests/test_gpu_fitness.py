@@ -28,7 +28,7 @@ def within(f_gpu, f_ref, t, rel=1e-5, floor=1e-7):
 
 def gpu_fitness(gg, basis, d, X, t, W, error_fn=0, R=0.49):
     P = max(2, W.shape[0])
-    cfg = gg.config(basis=basis, degree=d, population=P, tournament_k=min(3, P),
+    cfg = gg.config(basis=basis, degree=d, population=P, tournament_k=min(3, P), elitism=1,
                     error_fn=error_fn, tmse_R=R)
     Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
     td = torch.from_numpy(np.ascontiguousarray(t)).cuda()
