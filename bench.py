@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "chromosome×pattern evals/s (% MFMA peak); time-to-target MSE, plain vs chosen"
 FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fitness_f32_scale_traffic.json")
 
 
@@ -69,12 +70,122 @@ def cpu_baseline(prob, P, seconds=10.0):
                       f"of {P} chromosomes"}
 
 
+def time_fitness(gg, game, genes, n, reps, stream):
+    """Average duration (s) of one fitness launch (+ its finish kernel) on
+    the library's stream, timed with HIP events."""
+    import torch
+    f32 = torch.empty(n, dtype=torch.float32, device=genes.device)
+    gg.game_fitness(game.h, genes, n, f32)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        gg.game_fitness(game.h, genes, n, f32)
+    end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / 1e3 / reps
+
+
+def time_steps(game, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        game.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        game.step()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def form_bf16(gg, steps, warmup):
+    """Precision form: 1,000,000 patterns x 32 features, Chebyshev degree 8
+    (257 genes), population 4,096, BF16 operands with FP32 accumulation; the
+    error of the BF16 fitness against the float64 re-score of a sample."""
+    import torch
+    from paper_1304_0597_amd import datagen
+    prob = datagen.precision()
+    P = prob.population
+    dev = torch.device("cuda:0")
+    cfg = gg.config(basis=prob.basis, degree=prob.degree, population=P, precision=gg.GAME_BF16,
+                    seed=0, max_generations=1 << 30, target=-1.0)
+    game = gg.Game(cfg, torch.from_numpy(prob.X).to(dev), torch.from_numpy(prob.t).to(dev))
+    game.init_population()
+    stream = torch.cuda.current_stream()
+    elapsed = time_steps(game, steps, warmup)
+    pop, _ = game.population()
+    t_kernel = time_fitness(gg, game, pop, P, max(10, steps), stream)
+    flops = 2.0 * (prob.n_genes - 1) * P * prob.n_patterns
+    f16 = game.fitness(pop, with64=True)[1]
+    idx = torch.arange(0, P, P // 64, device=dev)
+    r64 = game.rescore64(pop[idx].contiguous())
+    rel = ((f16[idx] - r64).abs() / r64).cpu().numpy()
+    game.close()
+    achieved = flops / t_kernel / 1e12
+    return {"workload": "precision: 1,000,000 patterns x 32 features, Chebyshev degree 8 "
+                        "(257 genes), population 4,096, BF16 operands, FP32 accumulation",
+            "value": P * prob.n_patterns * steps / elapsed, "unit": "evals/s",
+            "ms_per_step": elapsed * 1e3 / steps, "dtype": "bf16",
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK_TFLOPS,
+                         "traffic": None, "kernel_ms": t_kernel * 1e3, "flops_per_launch": flops},
+            "error_vs_float64": {"max_rel": float(rel.max()), "median_rel": float(np.median(rel)),
+                                 "sample": f"{idx.numel()} chromosomes of the population, "
+                                           "float64 re-score on the GPU"}}
+
+
+def form_batched(gg, steps, warmup):
+    """Batched form: the 256 runs of the batched workload (sizes drawn from
+    seed 3) advanced together, FP32; the autotuner picks the work
+    decomposition, whose fitness launch it times with HIP events."""
+    import torch
+    from paper_1304_0597_amd import datagen
+    shapes = datagen.batched_shapes()
+    dev = torch.device("cuda:0")
+    problems, cfgs = [], []
+    evals = flops = 0.0
+    for i, sh in enumerate(shapes):
+        prob = datagen.batched_problem(sh, i, with_validation=False)
+        problems.append((torch.from_numpy(prob.X).to(dev), torch.from_numpy(prob.t).to(dev)))
+        cfgs.append(gg.config(basis=sh.basis, degree=sh.degree, population=sh.population,
+                              seed=i, max_generations=1 << 30, target=-1.0))
+        evals += sh.population * sh.n_patterns
+        flops += 2.0 * sh.n_features * sh.degree * sh.population * sh.n_patterns
+    batch = gg.Batch(problems, cfgs)
+    batch.init()
+    tune = batch.autotune(reps=3)
+    for _ in range(warmup):
+        batch.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_items, tiles, grid = batch.items()
+    batch.close()
+    t_kernel = tune["ms"] / 1e3
+    achieved = flops / t_kernel / 1e12
+    return {"workload": "batched: 256 independent runs, patterns 1e3-2e5 log-uniform, features "
+                        "4-64, degree 2-10, population 32-1024, Chebyshev/power, FP32 "
+                        "(sizes drawn from seed 3)",
+            "value": evals * steps / elapsed, "unit": "evals/s",
+            "ms_per_step": elapsed * 1e3 / steps, "dtype": "f32",
+            "evals_per_generation": evals,
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                         "traffic": None, "kernel_ms": t_kernel * 1e3, "flops_per_launch": flops},
+            "autotune": {"tiles_per_item": tiles, "grid": grid, "items": n_items,
+                         "times_ms": tune["times_ms"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the BF16, batched and surrogate workloads")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise kernel of known traffic (256 MiB read, "
                          "256 MiB written per launch) to scale hardware byte counters")
@@ -110,14 +221,7 @@ def main():
     game.init_population()
     stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        game.step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        game.step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed = time_steps(game, args.steps, args.warmup)
     st = game.state()
     assert st["stopped"] == 0, "the run stopped inside the timed region"
     ms_per_step = elapsed * 1e3 / args.steps
@@ -127,16 +231,7 @@ def main():
     # Dominant kernel: the fused fitness launch (plus its tiny finish kernel)
     # on the same stream and launch configuration, timed with HIP events.
     pop, _ = game.population()
-    f32 = torch.empty(P, dtype=torch.float32, device=dev)
-    reps = max(10, args.steps)
-    game.fitness(pop)
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    for _ in range(reps):
-        gg.game_fitness(game.h, pop, P, f32)
-    end.record(stream)
-    end.synchronize()
-    t_kernel = start.elapsed_time(end) / 1e3 / reps
+    t_kernel = time_fitness(gg, game, pop, P, max(10, args.steps), stream)
     Kf = prob.n_genes - 1
     flops = 2.0 * Kf * P * prob.n_patterns
     achieved = flops / t_kernel / 1e12
@@ -170,9 +265,13 @@ def main():
                      "traffic": traffic, "kernel_ms": t_kernel * 1e3,
                      "flops_per_launch": flops},
     }
+    game.close()
+    if not args.no_forms:
+        out["forms"] = {"bf16": form_bf16(gg, args.steps, args.warmup),
+                        "batched": form_batched(gg, max(5, args.steps // 5),
+                                                max(2, args.warmup // 5))}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, P)
-    game.close()
     print(json.dumps(out), flush=True)
 
 

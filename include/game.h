@@ -58,6 +58,10 @@ typedef enum { GAME_CHEBYSHEV = 0, GAME_LEGENDRE = 1, GAME_POWER = 2, GAME_TRIG 
  * squared residual with R as Eq. 10 is printed. */
 typedef enum { GAME_MSE = 0, GAME_RMSE = 1, GAME_TMSE = 2, GAME_TMSE_SQUARED = 3 } game_error_fn;
 
+/* Arithmetic of the fitness contraction: FP32 MFMA, or BF16 operands (genes
+ * and expansion values rounded to nearest even) with FP32 accumulation and
+ * a compensated reduction.  With GAME_BF16, game_run reports the elite's
+ * error re-scored in float64 (game_rescore64). */
 typedef enum { GAME_FP32 = 0, GAME_BF16 = 1 } game_precision;
 
 /* Initial population (the three random modes listed in Sec. 2): normal in
@@ -130,6 +134,14 @@ int game_fitness(game_t h, const float* genes_dev, int32_t n, float* fitness_dev
 int game_evaluate(game_t h, const float* X_dev, const float* t_dev, int64_t n_patterns,
                   const float* genes_dev, int32_t n, double* err64_dev);
 
+/* Float64 error of n chromosomes genes_dev [n x K] (Eqs. 2-5, 10 evaluated
+ * in double precision on the vector ALUs), err64_dev [n]: the elite's final
+ * re-score after a BF16 run, or an exact audit of any result.  X_dev/t_dev
+ * NULL means the handle's own data set (n_patterns is then ignored);
+ * 1 <= n <= population.  Deterministic (fixed-order sums). */
+int game_rescore64(game_t h, const float* X_dev, const float* t_dev, int64_t n_patterns,
+                   const float* genes_dev, int32_t n, double* err64_dev);
+
 /* Generation 0: random genes per cfg.init_mode (stream 0, unit =
  * chromosome, block = gene).  Resets the generation counter and stop flag. */
 int game_init_population(game_t h);
@@ -179,6 +191,144 @@ int game_ga_next(const game_config* cfg, int32_t n_genes, const float* pop_dev,
 
 /* Stateless generation-0 population [P x n_genes] (cfg.init_mode, cfg.seed). */
 int game_init_genes(const game_config* cfg, int32_t n_genes, float* out_dev, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Fitness surrogate: a multilayer perceptron (genes -> standardised log
+ * error; two hidden layers of `hidden` units with GELU, one output) trained
+ * on the GPU with Adam from an archive of the exact evaluations the GA
+ * makes.  Attached to a run it pre-screens offspring: each generation
+ * builds oversample x (P - E) children with the same draws as the plain
+ * genetic step (the first P - E of them are exactly the plain offspring),
+ * scores them with the network, and keeps the P - E best-predicted ones.
+ * An audit sample of `audit` randomly chosen children is scored exactly;
+ * when the Spearman rank correlation between its predicted and exact
+ * errors is below rho_min, or the archive holds fewer than min_archive
+ * chromosomes, that generation keeps the plain offspring instead.  Exact
+ * fitness remains the only selection criterion inside the population.
+ * ---------------------------------------------------------------------- */
+typedef struct game_surrogate_ctx* game_surrogate_t;
+
+typedef struct {
+  int32_t hidden;         /* units per hidden layer (256)                     */
+  int32_t fp32_operands;  /* 0: BF16 operands, FP32 accumulation; 1: FP32      */
+  int32_t archive;        /* archive capacity in chromosomes (65536)          */
+  int32_t minibatch;      /* rows per Adam step (1024)                        */
+  int32_t train_steps;    /* Adam steps per generation (4)                    */
+  float lr;               /* Adam learning rate (1e-3)                        */
+  int32_t oversample;     /* children generated per kept child (8)            */
+  int32_t audit;          /* children scored exactly per generation (64)      */
+  float rho_min;          /* rank correlation needed to screen (0.8)          */
+  int32_t min_archive;    /* archive size needed to screen (4096)             */
+  uint64_t seed;          /* initial weights and sampling draws (stream 3)    */
+} game_surrogate_config;
+
+int game_surrogate_config_default(game_surrogate_config* cfg);
+
+/* Workspace bytes for a surrogate over n_genes inputs that predicts up to
+ * max_batch rows at once (>= oversample x (P - E) to be attached). */
+size_t game_surrogate_workspace_size(const game_surrogate_config* cfg, int32_t n_genes,
+                                     int32_t max_batch);
+
+/* Creates the network with its initial weights (uniform in
+ * [-1/sqrt(fan_in), 1/sqrt(fan_in)) from Philox stream 3, zero biases) and
+ * zero Adam moments, on the stream. */
+int game_surrogate_create(const game_surrogate_config* cfg, int32_t n_genes, int32_t max_batch,
+                          void* workspace_dev, size_t workspace_bytes, void* hip_stream,
+                          game_surrogate_t* out);
+int game_surrogate_destroy(game_surrogate_t s);
+
+/* Number of parameters; they are one float32 vector in the order W1
+ * [hidden x n_genes], b1, W2 [hidden x hidden], b2, w3 [hidden], b3. */
+int64_t game_surrogate_num_params(game_surrogate_t s);
+int game_surrogate_get_params(game_surrogate_t s, float* params_dev);
+int game_surrogate_set_params(game_surrogate_t s, const float* params_dev);
+
+/* Predictions y_dev [n] for genes_dev [n x n_genes], 1 <= n <= max_batch. */
+int game_surrogate_predict(game_surrogate_t s, const float* genes_dev, int32_t n, float* y_dev);
+
+/* Gradients grads_dev [num_params] of mean((y - target)^2) over n rows
+ * (1 <= n <= minibatch), and the predictions y_dev [n] if not NULL. */
+int game_surrogate_gradients(game_surrogate_t s, const float* genes_dev, const float* target_dev,
+                             int32_t n, float* grads_dev, float* y_dev);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected) on those
+ * gradients. */
+int game_surrogate_train_step(game_surrogate_t s, const float* genes_dev, const float* target_dev,
+                              int32_t n);
+
+/* Attaches (or, with NULL, detaches) a surrogate to a run: its generations
+ * then screen offspring as described above.  The surrogate must have
+ * n_genes = K, max_batch >= oversample x (P - E), audit <= P and the same
+ * stream. */
+int game_attach_surrogate(game_t h, game_surrogate_t s);
+
+/* Synchronises and reports: rank correlation of the last audit, whether the
+ * last generation was screened, generations screened so far, archive
+ * size, Adam steps taken. */
+int game_surrogate_stats(game_surrogate_t s, float* rho, int32_t* screened_last,
+                         int32_t* screened_total, int32_t* archive_count, int32_t* adam_steps);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent runs of uneven sizes advanced together.  Each
+ * generation is one persistent fitness launch over a work list of (run,
+ * 64-chromosome tile, pattern split) items drained through an atomic queue,
+ * one rank/stop-test launch and one genetic-step launch for all runs;
+ * game_batch_run replays a captured HIP graph of such generations.  Every
+ * run follows exactly the trajectory it would follow alone (same draws,
+ * same fixed-order sums).  FP32 precision only.
+ * ---------------------------------------------------------------------- */
+typedef struct game_batch_ctx* game_batch_t;
+
+typedef struct {
+  const float* X_dev;     /* [n_patterns x n_features], caller-owned          */
+  const float* t_dev;     /* [n_patterns]                                     */
+  int64_t n_patterns;
+  int32_t n_features;
+  int32_t reserved;       /* set to 0                                         */
+  game_config cfg;        /* the run's own configuration (precision FP32)     */
+} game_run_desc;
+
+/* Workspace bytes for a batch of n_runs runs (0 if a run is invalid). */
+size_t game_batch_workspace_size(const game_run_desc* runs, int32_t n_runs);
+
+/* Creates a batch over caller-owned data; the workspace (256-byte aligned,
+ * game_batch_workspace_size bytes) holds every run's populations, fitness,
+ * partial sums and the work list.  Copies the descriptors; synchronises
+ * the stream once.  The default decomposition is 8 tiles of 256 patterns
+ * per item and 512 persistent workgroups. */
+int game_batch_create(const game_run_desc* runs, int32_t n_runs, void* workspace_dev,
+                      size_t workspace_bytes, void* hip_stream, game_batch_t* out);
+int game_batch_destroy(game_batch_t b);
+
+/* Sets the work decomposition: patterns per item in 256-row tiles, and the
+ * number of persistent fitness workgroups.  Synchronises the stream. */
+int game_batch_tune(game_batch_t b, int32_t tiles_per_item, int32_t grid);
+
+/* The batch autotuner: times the batch's fitness launch (HIP events, reps
+ * launches each) for every tiles_per_item in {1,2,4,8,16,32} and grid in
+ * {256,512,1024}, keeps the fastest and reports it; times_ms (may be NULL)
+ * receives the 18 averages in that order.  Leaves the populations as they
+ * were.  Synchronises the stream. */
+int game_batch_autotune(game_batch_t b, int32_t reps, int32_t* tiles_per_item, int32_t* grid,
+                        float* best_ms, float* times_ms);
+
+/* Generation 0 of every run (its own init_mode and seed). */
+int game_batch_init(game_batch_t b);
+
+/* One generation of every run that has not stopped (three launches). */
+int game_batch_step(game_batch_t b);
+
+/* Runs every run until its stop criterion holds (its own max_generations
+ * and target), by graph replay; synchronises.  Outputs per run (may be
+ * NULL): evolution steps applied, best float64 error of the last
+ * evaluation. */
+int game_batch_run(game_batch_t b, int32_t* generations_done_host, double* best_error_host);
+
+/* Current population [P x K] of one run and its last fitness [P]. */
+int game_batch_get_population(game_batch_t b, int32_t run, float* genes_dev, float* fitness_dev);
+
+/* Current work decomposition: number of items, tiles per item, grid. */
+int game_batch_num_items(game_batch_t b, int32_t* n_items, int32_t* tiles_per_item, int32_t* grid);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* game_last_error(void);

@@ -68,6 +68,28 @@ void plan_fitness(FitArgs& a, int degree, int basis);
 size_t fitness_lds_bytes(const FitArgs& a, int degree);
 
 hipError_t launch_fitness_f32(const FitArgs& a, int basis, int degree, hipStream_t s);
+// BF16 operands, FP32 accumulation: 128-chromosome tiles; in its plan Q
+// counts groups of sub-features and pairs_per_chunk the groups per chunk.
+void plan_fitness_bf16(FitArgs& a, int degree, int basis);
+hipError_t launch_fitness_bf16(const FitArgs& a, int basis, int degree, hipStream_t s);
+constexpr int kMaxTileCols = 128;
+
+// Float64 re-score of n chromosomes over a data set.
+struct Rescore64Args {
+  const float* X;
+  const float* t;
+  const float* genes;
+  double* partial;          // [blocks x n]
+  int64_t NP;
+  int32_t N;
+  int32_t K;
+  int32_t n;
+  int32_t blocks;
+  int32_t error_fn;
+  double R;
+};
+hipError_t launch_rescore64(const Rescore64Args& a, int basis, int degree, double* out,
+                            hipStream_t s);
 hipError_t launch_finish(const double* partial, int32_t ld, int32_t n, int32_t n_splits, int64_t NP,
                          int32_t error_fn, float* f32, double* f64, hipStream_t s);
 hipError_t launch_init_genes(uint64_t seed, int32_t mode, int32_t P, int32_t K, float* out,
@@ -93,6 +115,8 @@ struct GAArgs {
   uint64_t thr_mut;
   float sigma;
   uint64_t seed;
+  int32_t n_slots;          // output slots incl. elites; 0 means P
+  float* children;          // when set, child slot s goes to row s - E here
 };
 hipError_t launch_ga_next(const GAArgs& a, hipStream_t s);
 
@@ -115,5 +139,139 @@ constexpr int kRankThreads = 1024;
 constexpr int kRankPerBlock = 64;
 hipError_t launch_set_state(RunState* st, int32_t gen, int32_t max_gen, double target,
                             int32_t reset, hipStream_t s);
+
+// ---------------------------------------------------------------- batches
+// One run of a batch: its data, its fitness plan (float32 kernel geometry),
+// its population buffers and its genetic parameters.
+struct BatchRun {
+  const float* X;
+  const float* t;
+  int64_t NP;
+  int32_t N;
+  int32_t K;
+  int32_t basis;
+  int32_t D;
+  int32_t U;
+  int32_t Q;
+  int32_t pairs_per_chunk;
+  int32_t n_chunks;
+  int32_t n_ctiles;
+  int32_t ld_partial;
+  int32_t n_splits;
+  int32_t tiles_per_split;
+  int32_t n_tiles;
+  int32_t error_fn;
+  float R;
+  float* pop0;
+  float* pop1;
+  float* fit32;
+  double* fit64;
+  int32_t* order;
+  double* partial;
+  RunState* state;
+  int32_t P;
+  int32_t k;
+  int32_t E;
+  int32_t elite_mode;
+  uint64_t thr_cross;
+  uint64_t thr_mut;
+  float sigma;
+  uint64_t seed;
+  int32_t rank_block0;      // first rank workgroup of this run
+  int32_t ga_wave0;         // first genetic-step wave of this run
+};
+
+// A unit of fitness work: one 64-chromosome tile of one run over one split
+// of its patterns.
+struct BatchItem {
+  int32_t run;
+  int32_t ctile;
+  int32_t split;
+  int32_t cost;             // relative work, for ordering
+};
+
+struct BatchArgs {
+  const BatchRun* runs;
+  const BatchItem* items;
+  int32_t* counter;         // work-queue head of the fitness launch
+  const int32_t* rank_block_run;
+  const int32_t* ga_wave_run;
+  int32_t n_runs;
+  int32_t n_items;
+  int32_t n_rank_blocks;
+  int32_t n_ga_waves;
+  int32_t max_population;
+  int32_t grid;             // persistent fitness workgroups
+};
+hipError_t launch_fitness_batch(const BatchArgs& a, size_t lds_bytes, hipStream_t s);
+hipError_t launch_finish_rank_batch(const BatchArgs& a, hipStream_t s);
+hipError_t launch_ga_next_batch(const BatchArgs& a, hipStream_t s);
+hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- surrogate
+struct GemmArgs {
+  const float* A;           // A(m, k) = A[m * lda_m + k * lda_k]
+  const float* B;           // B(n, k) = B[n * ldb_n + k * ldb_k]
+  float* C;                 // C[m * ldc + n]
+  const float* bias;        // [N] or null
+  float* Z;                 // pre-activation out (act 1) or null
+  const float* aux;         // act 2: C *= gelu'(aux[m * ld_aux + n])
+  int64_t lda_m, lda_k, ldb_n, ldb_k, ldc, ld_aux;
+  int32_t M, N, K;
+  int32_t act;              // 0 none, 1 GELU, 2 times GELU'(aux)
+  const int32_t* skip;      // when set and nonzero the launch does nothing
+};
+hipError_t launch_gemm(const GemmArgs& g, bool bf16, hipStream_t s);
+hipError_t launch_colsum(const float* A, int M, int N, int ld, float* out, const int32_t* skip,
+                         hipStream_t s);
+hipError_t launch_out_grad(const float* y, const float* t, int B, const float* w3, const float* Z2,
+                           int H, float* dy, float* dZ2, const int32_t* skip, hipStream_t s);
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+
+struct SurrogateState {
+  int32_t step;             // Adam steps taken
+  float c1, c2;             // Adam bias corrections of the current step
+  int32_t head;             // archive ring position of the next append
+  int32_t count;            // archive entries
+  float mean, inv_std;      // standardisation of the archive targets
+  float rho;                // Spearman correlation of the last audit
+  int32_t use;              // 1 when this generation's offspring are screened
+  int32_t screened;         // generations screened so far
+  int32_t pad[6];
+};
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                       SurrogateState* st, const int32_t* skip, hipStream_t s);
+
+// Surrogate kernels built with the Philox draws (stream 3).
+hipError_t launch_mlp_init(float* params, int n_in, int hidden, uint64_t seed, hipStream_t s);
+struct ArchiveArgs {
+  const RunState* run;      // the evaluated generation is run->evaluated
+  const float* pop0;
+  const float* pop1;
+  const double* fit64;
+  int32_t P;
+  int32_t K;
+  float* genes;             // [capacity x K]
+  float* target;            // [capacity] log error
+  int32_t capacity;
+  SurrogateState* st;
+};
+hipError_t launch_archive_append(const ArchiveArgs& a, hipStream_t s);
+hipError_t launch_archive_stats(const float* target, SurrogateState* st, const RunState* run,
+                                int P, int capacity, hipStream_t s);
+hipError_t launch_sample_minibatch(const float* genes, const float* target, int32_t K,
+                                   const SurrogateState* st, const RunState* run, uint64_t seed,
+                                   int32_t step, int32_t B, float* Xb, float* tb, hipStream_t s);
+hipError_t launch_audit_pick(const float* cand, const float* pred, int32_t C, int32_t K,
+                             const RunState* run, uint64_t seed, int32_t A, float* genes,
+                             float* pred_out, hipStream_t s);
+hipError_t launch_spearman_gate(const float* pred, const float* exact, int32_t A, float rho_min,
+                                int32_t min_archive, const RunState* run, SurrogateState* st,
+                                hipStream_t s);
+hipError_t launch_rank_large(const float* v, int32_t n, int32_t* rank, const RunState* run,
+                             hipStream_t s);
+hipError_t launch_gather_next(const float* cand, const int32_t* rank, int32_t C, int32_t K,
+                              int32_t E, int32_t P, const RunState* run, const SurrogateState* st,
+                              float* pop0, float* pop1, hipStream_t s);
 
 }  // namespace game

@@ -1,0 +1,353 @@
+// Fused GAME fitness with BF16 operands on MFMA (gfx950), FP32 accumulation.
+//
+// Same contraction as the float32 kernel (Eq. 2 over NP patterns, then the
+// error of Eqs. 3-5/10), with the expansion values and the genes rounded to
+// bfloat16 (round to nearest even) and fed to v_mfma_f32_32x32x16_bf16;
+// products accumulate in float32.  The bias gene stays float32 and is added
+// to the accumulated sum in the epilogue.  Squared
+// residuals are summed in float32 per tile and the tile sums are added with
+// Neumaier compensation, so the reduction over a million patterns adds no
+// error beyond the per-tile float32 sums.
+//
+// Operand layout: in a K-step each lane supplies 8 consecutive K values of
+// its pattern row (A) and of its chromosome column (B).  The two lane halves
+// carry different sub-features, so a lane's 8 values are consecutive members
+// phi_j of its own recurrence chains: a group of G sub-features per lane
+// half (a multiple of 8 / gcd(d, 8)) fills exactly G*d/8 K-steps and no
+// chain is split between lanes.  Genes are staged in LDS in that order as
+// bfloat16.
+//
+// Tiles: a workgroup covers 256 patterns x 128 chromosomes; each wave 64
+// patterns (two 32-row blocks) x 128 chromosomes (four 32-column blocks),
+// eight 32x32 accumulators, so each generated A fragment feeds four MFMAs.
+#include <utility>
+
+#include "basis.h"
+#include "common.h"
+
+namespace game {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
+
+// Sub-features per lane half in one group: the smallest count whose d values
+// fill whole K-steps of 8, repeated until a group spans at least 4 K-steps
+// (so the next group's features load, and its first values are generated,
+// while this group's MFMAs run), at most 16.
+constexpr int group_size(int d) {
+  const int g0 = 8 / gcd_int(d, 8);
+  const int ks0 = g0 * d / 8;
+  int r = ks0 >= 4 ? 1 : (4 + ks0 - 1) / ks0;
+  while (g0 * r > 16) --r;
+  return g0 * r;
+}
+
+// LDS row stride for one chromosome: 32 bytes per K-step (two lane halves x
+// 8 bf16) plus 16 bytes so that rows start 4 banks apart.
+__host__ __device__ constexpr int bf16_row_bytes(int ksteps) { return ksteps * 32 + 16; }
+
+template <int BASIS, int D>
+__global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a) {
+  constexpr int G = group_size(D);         // sub-features per lane half per group
+  constexpr int KS = G * D / 8;            // K-steps per group
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  if (a.stop) {
+    const int32_t stopped = *a.stop;
+    if (a.stop_seen && blockIdx.x == 0 && threadIdx.x == 0) *a.stop_seen = stopped;
+    if (stopped) return;
+  }
+  const float* __restrict__ genes = a.genes;
+  if (a.gen_sel && (*a.gen_sel & 1)) genes = a.genes_alt;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int m = lane & 31;
+  const int h = lane >> 5;
+
+  const int total = gridDim.x;
+  const int b = blockIdx.x;
+  const int L = a.xcd_remap ? (b & 7) * (total >> 3) + (b >> 3) : b;
+  const int split = L / a.n_ctiles;
+  const int ctile = L - split * a.n_ctiles;
+  constexpr int kCols = 128;
+  const int c0 = ctile * kCols;
+
+  const int gpc = a.pairs_per_chunk;       // groups per chunk
+  const int ks_chunk = gpc * KS;           // K-steps per chunk
+  const int RS = bf16_row_bytes(ks_chunk); // LDS row stride in bytes
+  const int K = a.K;
+
+  float w0[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int n = c0 + cb * 32 + m;
+    w0[cb] = n < a.n_chrom ? genes[(int64_t)n * K] : 0.f;
+  }
+
+  // Stage groups [chunk*gpc, chunk*gpc + gpc): value p (0..G*D-1) of lane
+  // half hh in group g is gene (sub-feature u = 2(g*G + p/D) + hh, degree
+  // p%D + 1); it goes to byte (kstep*32 + hh*16 + (p%8)*2) of the row.
+  auto stage = [&](int chunk) {
+    const int per_row = gpc * 2 * G * D;   // values per chromosome row
+    for (int idx = threadIdx.x; idx < kCols * per_row; idx += kFitThreads) {
+      const int c = idx / per_row;
+      const int r = idx - c * per_row;
+      const int gl = r / (2 * G * D);      // group within the chunk
+      const int r2 = r - gl * (2 * G * D);
+      const int hh = r2 / (G * D);
+      const int p = r2 - hh * (G * D);
+      const int qi = (chunk * gpc + gl) * G + p / D;
+      const int j = p % D;
+      const int u = 2 * qi + hh;
+      const int n = c0 + c;
+      float v = 0.f;
+      if (n < a.n_chrom && u < a.U) v = genes[(int64_t)n * K + 1 + u * D + j];
+      const int ks = gl * KS + p / 8;
+      __bf16* dst = reinterpret_cast<__bf16*>(lds_raw + c * RS + ks * 32 + hh * 16) + (p & 7);
+      *dst = (__bf16)v;
+    }
+  };
+
+  if (a.n_chunks == 1) {
+    stage(0);
+    __syncthreads();
+  }
+
+  // Neumaier-compensated running sums of the per-tile float32 sums.
+  float sum[4] = {0.f, 0.f, 0.f, 0.f}, comp[4] = {0.f, 0.f, 0.f, 0.f};
+  const int64_t NP = a.NP;
+  const int N = a.N;
+  const int tile_begin = split * a.tiles_per_split;
+  const int tile_end = min(tile_begin + a.tiles_per_split, a.n_tiles);
+
+  // x of the G sub-features of group g for this lane's two rows.
+  auto load_x = [&](int64_t row0, int g, float (&xo)[2][G]) {
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const int qi = g * G + i;
+      const int u = 2 * qi + h;
+      const int f = BASIS == 3 ? qi : u;
+      const bool fvalid = BASIS == 3 ? (qi < N) : (u < a.U);
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const int64_t r = row0 + rb * 32 + m;
+        xo[rb][i] = (r < NP && fvalid) ? a.X[r * N + f] : 0.f;
+      }
+    }
+  };
+
+  const bool key_sq = a.error_fn == 3;
+  const bool tube = a.error_fn == 2 || a.error_fn == 3;
+  const float thr = a.R;
+
+  float xn[2][G];
+  if (tile_begin < tile_end) load_x((int64_t)tile_begin * kTileRows + wave * 64, 0, xn);
+  const int n_groups = a.Q;
+
+  // B fragments of this lane for the four column blocks at a K-step's byte
+  // offset within the chunk.
+  const unsigned char* wrow = lds_raw + m * RS + h * 16;
+  const int chunk_bytes = ks_chunk * 32;
+  auto load_b = [&](int kbyte, bf16x8 (&bo)[4]) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+      bo[cb] = *reinterpret_cast<const bf16x8*>(wrow + cb * 32 * RS + kbyte);
+  };
+  bf16x8 bcur[4];
+  if (a.n_chunks == 1) load_b(0, bcur);
+
+  for (int tile = tile_begin; tile < tile_end; ++tile) {
+    const int64_t row0 = (int64_t)tile * kTileRows + wave * 64;
+    const float t_lane = a.t[row0 + lane < NP ? row0 + lane : NP - 1];
+    // Accumulators start at zero (an inline constant, nothing to keep live
+    // across tiles); the bias joins in the epilogue.
+    f32x16 acc[2][4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      acc[0][cb] = f32x16{};
+      acc[1][cb] = f32x16{};
+    }
+
+    for (int chunk = 0; chunk < a.n_chunks; ++chunk) {
+      if (a.n_chunks > 1) {
+        __syncthreads();
+        stage(chunk);
+        __syncthreads();
+        load_b(0, bcur);
+      }
+      const int g_begin = chunk * gpc;
+      const int g_end = min(g_begin + gpc, n_groups);
+      for (int g = g_begin; g < g_end; ++g) {
+        float x[2][G];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int i = 0; i < G; ++i) x[rb][i] = xn[rb][i];
+        if (g + 1 < n_groups) load_x(row0, g + 1, xn);
+        else if (tile + 1 < tile_end) load_x(row0 + kTileRows, 0, xn);
+
+        const int kbase = (g - g_begin) * KS * 32;
+        bf16x8 av[2][2];
+        Recur<BASIS> rc[2];
+        // Walk the group's G*D values in order; every 8th value completes a
+        // K-step: prefetch the next K-step's B fragments (wrapping to the
+        // chunk's first one at its end), then issue eight MFMAs.  A
+        // fragments alternate between two buffers so the next K-step's
+        // values can be generated while these MFMAs run.
+        auto value = [&](auto pc) {
+          constexpr int p = decltype(pc)::value;
+          constexpr int i = p / D;
+          constexpr int j = p % D;
+          constexpr int ks = p / 8;
+          if constexpr (j == 0) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) rc[rb].seed(x[rb][i], h);
+          }
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb) av[ks & 1][rb][p & 7] = (__bf16)rc[rb].cur;
+          if constexpr (j + 1 < D) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) rc[rb].template advance<j + 1>(x[rb][i]);
+          }
+          if constexpr ((p & 7) == 7) {
+            int nb = kbase + (ks + 1) * 32;
+            nb = nb == chunk_bytes ? 0 : nb;
+            bf16x8 bnext[4];
+            load_b(nb, bnext);
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+              acc[0][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[ks & 1][0], bcur[cb], acc[0][cb], 0, 0, 0);
+              acc[1][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[ks & 1][1], bcur[cb], acc[1][cb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) bcur[cb] = bnext[cb];
+          }
+        };
+        [&]<int... P>(std::integer_sequence<int, P...>) {
+          (value(std::integral_constant<int, P>{}), ...);
+        }(std::make_integer_sequence<int, G * D>{});
+      }
+    }
+
+    // Epilogue, one code path for every error function: with the
+    // convergence tube (TMSE) the squared residual counts when its key
+    // exceeds R (key |r|, or r^2 for the printed form of Eq. 10); MSE and
+    // RMSE keep every term, so a NaN residual propagates to the sum.
+    const bool full = row0 + 64 <= NP;
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int rl = rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+        const float tv = __shfl(t_lane, rl);
+        const bool ok = full || (row0 + rl < NP);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          const float v = (acc[rb][cb][i] + w0[cb]) - tv;
+          const float e = v * v;
+          const float key = key_sq ? e : fabsf(v);
+          const float kept = tube ? (key > thr ? e : 0.f) : e;
+          s[cb] += ok ? kept : 0.f;
+        }
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const float t2 = sum[cb] + s[cb];
+      comp[cb] += fabsf(sum[cb]) >= fabsf(s[cb]) ? (sum[cb] - t2) + s[cb] : (s[cb] - t2) + sum[cb];
+      sum[cb] = t2;
+    }
+  }
+
+  double acc64[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    acc64[cb] = (double)sum[cb] + (double)comp[cb];
+    acc64[cb] += __shfl_xor(acc64[cb], 32);
+  }
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(lds_raw);
+  if (h == 0) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) red[wave * kCols + cb * 32 + m] = acc64[cb];
+  }
+  __syncthreads();
+  if (threadIdx.x < kCols) {
+    const int c = threadIdx.x;
+    const double v = ((red[c] + red[kCols + c]) + red[2 * kCols + c]) + red[3 * kCols + c];
+    a.partial[(int64_t)split * a.ld_partial + c0 + c] = v;
+  }
+}
+
+size_t fitness_bf16_lds_bytes(const FitArgs& a, int degree) {
+  const int G = group_size(degree);
+  const int KS = G * degree / 8;
+  const size_t w = (size_t)128 * bf16_row_bytes(a.pairs_per_chunk * KS);
+  const size_t red = 4 * 128 * sizeof(double);
+  return w > red ? w : red;
+}
+
+// Plan: Q = number of groups of 2G sub-features; pairs_per_chunk = groups
+// staged in LDS at once (at most 16 K-steps); 128-chromosome tiles.
+void plan_fitness_bf16(FitArgs& a, int degree, int basis) {
+  const int G = group_size(degree);
+  const int KS = G * degree / 8;
+  a.U = (basis == 3 ? 2 : 1) * a.N;
+  a.Q = (a.U + 2 * G - 1) / (2 * G);
+  int gpc = 16 / KS;
+  if (gpc < 1) gpc = 1;
+  if (gpc > a.Q) gpc = a.Q;
+  a.pairs_per_chunk = gpc;
+  a.n_chunks = (a.Q + gpc - 1) / gpc;
+  a.n_ctiles = (a.n_chrom + 127) / 128;
+  a.ld_partial = a.n_ctiles * 128;
+  a.n_tiles = (int32_t)((a.NP + kTileRows - 1) / kTileRows);
+  const int target = 512;
+  int splits = (target + a.n_ctiles - 1) / a.n_ctiles;
+  if (splits > kMaxSplits) splits = kMaxSplits;
+  if (splits > a.n_tiles) splits = a.n_tiles;
+  if (splits < 1) splits = 1;
+  a.tiles_per_split = (a.n_tiles + splits - 1) / splits;
+  a.n_splits = (a.n_tiles + a.tiles_per_split - 1) / a.tiles_per_split;
+  a.xcd_remap = ((a.n_ctiles * a.n_splits) % 8) == 0 ? 1 : 0;
+}
+
+template <int BASIS, int D>
+static hipError_t launch_one(const FitArgs& a, hipStream_t s) {
+  const size_t lds = fitness_bf16_lds_bytes(a, D);
+  const int grid = a.n_ctiles * a.n_splits;
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)fitness_bf16_kernel<BASIS, D>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((fitness_bf16_kernel<BASIS, D>), dim3(grid), dim3(kFitThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int BASIS>
+static hipError_t launch_basis(const FitArgs& a, int degree, hipStream_t s) {
+  switch (degree) {
+#define GAME_CASE(D) case D: return launch_one<BASIS, D>(a, s);
+    GAME_CASE(1) GAME_CASE(2) GAME_CASE(3) GAME_CASE(4) GAME_CASE(5) GAME_CASE(6)
+    GAME_CASE(7) GAME_CASE(8) GAME_CASE(9) GAME_CASE(10) GAME_CASE(11) GAME_CASE(12)
+    GAME_CASE(13) GAME_CASE(14) GAME_CASE(15) GAME_CASE(16)
+#undef GAME_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fitness_bf16(const FitArgs& a, int basis, int degree, hipStream_t s) {
+  switch (basis) {
+    case 0: return launch_basis<0>(a, degree, s);
+    case 1: return launch_basis<1>(a, degree, s);
+    case 2: return launch_basis<2>(a, degree, s);
+    case 3: return launch_basis<3>(a, degree, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace game

@@ -16,9 +16,10 @@
 //  * The B operand (K x chromosomes) is staged once per workgroup in LDS in
 //    that permuted order (odd row stride: conflict-free ds_read_b32).  When
 //    K does not fit, it is staged in chunks of whole feature pairs.
-//  * Accumulators start at a_0(p) - t_k, so after the K loop they hold
-//    Out - t; the epilogue squares, applies the error function and sums the
-//    lane's 32 rows in float32, then adds into a float64 running sum.
+//  * Accumulators start at zero; the epilogue adds the bias a_0(p), takes
+//    the residual against t_k, squares it (or applies the error function)
+//    and sums the lane's 32 rows in float32, then adds into a float64
+//    running sum.
 //    Partials per (chromosome, split) are combined in a fixed order: the
 //    result does not depend on scheduling.
 //  * Grid: (pattern split) x (64-chromosome tile); consecutive blocks of one
@@ -26,59 +27,12 @@
 //    chromosome tiles.
 #include <utility>
 
+#include "basis.h"
 #include "common.h"
 
 namespace game {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-template <int BASIS>
-struct Recur;
-
-// Chebyshev: T_{j+1} = 2x T_j - T_{j-1}
-template <>
-struct Recur<0> {
-  float prev, cur, m2;
-  __device__ void seed(float x, int) { prev = 1.f; cur = x; m2 = 2.f * x; }
-  template <int J>
-  __device__ void advance(float) { float n = fmaf(m2, cur, -prev); prev = cur; cur = n; }
-};
-// Legendre: (j+1) P_{j+1} = (2j+1) x P_j - j P_{j-1}
-template <>
-struct Recur<1> {
-  float prev, cur;
-  __device__ void seed(float x, int) { prev = 1.f; cur = x; }
-  template <int J>
-  __device__ void advance(float x) {
-    constexpr float a = float(2 * J + 1) / float(J + 1);
-    constexpr float b = float(J) / float(J + 1);
-    float n = fmaf(a * x, cur, -b * prev);
-    prev = cur; cur = n;
-  }
-};
-// Powers: x^{j+1} = x * x^j
-template <>
-struct Recur<2> {
-  float cur;
-  __device__ void seed(float x, int) { cur = x; }
-  template <int J>
-  __device__ void advance(float x) { cur *= x; }
-};
-// Trigonometric (Eq. 8): cos/sin((j+1)x) = 2 cos x * cos/sin(jx) - cos/sin((j-1)x).
-// Lane half 0 runs the cos chain, half 1 the sin chain of the same feature.
-template <>
-struct Recur<3> {
-  float prev, cur, m2;
-  __device__ void seed(float x, int half) {
-    float s, c;
-    sincosf(x, &s, &c);
-    prev = half ? 0.f : 1.f;
-    cur = half ? s : c;
-    m2 = 2.f * c;
-  }
-  template <int J>
-  __device__ void advance(float) { float n = fmaf(m2, cur, -prev); prev = cur; cur = n; }
-};
 
 // Squared residual (MSE, RMSE) or its thresholded form (TMSE, Eq. 10):
 // mode 2 keeps it when |r| > R, mode 3 when r^2 > R.
@@ -174,14 +128,13 @@ __global__ __launch_bounds__(kFitThreads, 2) void fitness_f32_kernel(FitArgs a) 
     // One target per lane (the wave's 64 rows); the epilogue redistributes
     // them across lanes, so the load's latency hides behind the K loop.
     const float t_lane = a.t[row0 + lane < NP ? row0 + lane : NP - 1];
+    // Accumulators start at zero (an inline constant, nothing to keep live
+    // across tiles); the bias joins in the epilogue.
     f32x16 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      acc[0][0][i] = w0[0];
-      acc[0][1][i] = w0[1];
-      acc[1][0][i] = w0[0];
-      acc[1][1][i] = w0[1];
-    }
+    acc[0][0] = f32x16{};
+    acc[0][1] = f32x16{};
+    acc[1][0] = f32x16{};
+    acc[1][1] = f32x16{};
 
     for (int chunk = 0; chunk < a.n_chunks; ++chunk) {
       if (a.n_chunks > 1) {
@@ -235,8 +188,8 @@ __global__ __launch_bounds__(kFitThreads, 2) void fitness_f32_kernel(FitArgs a) 
         for (int i = 0; i < 16; ++i) {
           const int rl = rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
           const float tv = __shfl(t_lane, rl);
-          float e0 = error_term<mode>(acc[rb][0][i] - tv, a.R);
-          float e1 = error_term<mode>(acc[rb][1][i] - tv, a.R);
+          float e0 = error_term<mode>((acc[rb][0][i] + w0[0]) - tv, a.R);
+          float e1 = error_term<mode>((acc[rb][1][i] + w0[1]) - tv, a.R);
           if (!full) {
             const bool ok = row0 + rl < NP;
             e0 = ok ? e0 : 0.f;

@@ -174,13 +174,12 @@ __device__ __forceinline__ double error_of(const RankArgs& a, int i) {
 // decides whether this launch works is the one the generation's fitness
 // launch recorded, so a workgroup that sets the flag cannot make another
 // workgroup of the same launch skip its share.
-__global__ __launch_bounds__(kRankThreads) void finish_rank_kernel(RankArgs a) {
-  extern __shared__ uint64_t keys[];
-  __shared__ uint32_t cnt[kRankThreads];
+// Body of one rank workgroup; `blk` is the workgroup's index within the run.
+__device__ void finish_rank_body(const RankArgs& a, int blk, uint64_t* keys, uint32_t* cnt) {
   RunState* st = a.state;
   if (st->stop_seen) return;
   const int P = a.P;
-  const int lo = blockIdx.x * kRankPerBlock;
+  const int lo = blk * kRankPerBlock;
   for (int i = threadIdx.x; i < P; i += blockDim.x) {
     const double v = error_of(a, i);
     const float f = (float)v;
@@ -207,6 +206,12 @@ __global__ __launch_bounds__(kRankThreads) void finish_rank_kernel(RankArgs a) {
       st->gen = gen + 1;
     }
   }
+}
+
+__global__ __launch_bounds__(kRankThreads) void finish_rank_kernel(RankArgs a) {
+  extern __shared__ uint64_t keys[];
+  __shared__ uint32_t cnt[kRankThreads];
+  finish_rank_body(a, blockIdx.x, keys, cnt);
 }
 
 hipError_t launch_finish_rank(const RankArgs& a, hipStream_t s) {
@@ -263,7 +268,9 @@ __device__ __forceinline__ int tournament(const float* fit, const uint32_t* w, i
 
 constexpr int kMaxTournament = 64;
 
-__global__ __launch_bounds__(256) void ga_next_kernel(GAArgs a) {
+// Body of one wave: output group `wid` (an elite slot, or child pair
+// wid - E) of the run described by `a`.
+__device__ void ga_next_wave(const GAArgs& a, int wid) {
   if (a.stop && *a.stop) return;
   int gen;
   const float* __restrict__ pop;
@@ -278,9 +285,9 @@ __global__ __launch_bounds__(256) void ga_next_kernel(GAArgs a) {
     out = a.out_a;
   }
   const int lane = threadIdx.x & 63;
-  const int wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int P = a.P, K = a.K, E = a.E;
-  const int n_pairs = (P - E + 1) >> 1;
+  const int n_slots = a.n_slots ? a.n_slots : P;
+  const int n_pairs = (n_slots - E + 1) >> 1;
   if (wid < E) {
     const int src = a.elite_mode == 0 ? a.order[0] : a.order[wid];
     for (int g = lane; g < K; g += 64) out[(int64_t)wid * K + g] = pop[(int64_t)src * K + g];
@@ -307,7 +314,9 @@ __global__ __launch_bounds__(256) void ga_next_kernel(GAArgs a) {
   const int cut = 1 + (int)(((uint64_t)w[2 * a.k + 1] * (uint64_t)(K - 1)) >> 32);
 
   const int sa = E + 2 * q, sb = sa + 1;
-  const bool has_b = sb < P;
+  const bool has_b = sb < n_slots;
+  float* __restrict__ out_a = a.children ? a.children + (int64_t)(sa - E) * K : out + (int64_t)sa * K;
+  float* __restrict__ out_b = a.children ? a.children + (int64_t)(sb - E) * K : out + (int64_t)sb * K;
   for (int g = lane; g < K; g += 64) {
     const float x1 = pop[(int64_t)p1 * K + g];
     const float x2 = pop[(int64_t)p2 * K + g];
@@ -319,19 +328,385 @@ __global__ __launch_bounds__(256) void ga_next_kernel(GAArgs a) {
       if ((r.o0 & 0xFFFFFFFFull) < a.thr_mut)
         ca = clamp_unit(__fadd_rn(ca, __fmul_rn(a.sigma, gauss12(r))));
     }
-    out[(int64_t)sa * K + g] = ca;
+    out_a[g] = ca;
     if (has_b) {
       const U64x4 r = draw(a.seed, 2, (uint64_t)gen, (uint64_t)sb, (uint64_t)g);
       if ((r.o0 & 0xFFFFFFFFull) < a.thr_mut)
         cb = clamp_unit(__fadd_rn(cb, __fmul_rn(a.sigma, gauss12(r))));
-      out[(int64_t)sb * K + g] = cb;
+      out_b[g] = cb;
     }
   }
 }
 
+__global__ __launch_bounds__(256) void ga_next_kernel(GAArgs a) {
+  ga_next_wave(a, blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+}
+
 hipError_t launch_ga_next(const GAArgs& a, hipStream_t s) {
-  const int n_waves = a.E + ((a.P - a.E + 1) >> 1);
+  const int n_slots = a.n_slots ? a.n_slots : a.P;
+  const int n_waves = a.E + ((n_slots - a.E + 1) >> 1);
   hipLaunchKernelGGL(ga_next_kernel, dim3((n_waves + 3) / 4), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- batches
+__device__ RankArgs rank_args_of(const BatchRun& r) {
+  RankArgs a{};
+  a.partial = r.partial;
+  a.ld_partial = r.ld_partial;
+  a.n_splits = r.n_splits;
+  a.NP = r.NP;
+  a.P = r.P;
+  a.error_fn = r.error_fn;
+  a.fit32 = r.fit32;
+  a.fit64 = r.fit64;
+  a.order = r.order;
+  a.state = r.state;
+  return a;
+}
+
+// Rank workgroups of every run in one launch; workgroup b serves run
+// rank_block_run[b].
+__global__ __launch_bounds__(kRankThreads) void finish_rank_batch_kernel(BatchArgs a) {
+  extern __shared__ uint64_t keys[];
+  __shared__ uint32_t cnt[kRankThreads];
+  const int r = a.rank_block_run[blockIdx.x];
+  const BatchRun& run = a.runs[r];
+  finish_rank_body(rank_args_of(run), blockIdx.x - run.rank_block0, keys, cnt);
+}
+
+hipError_t launch_finish_rank_batch(const BatchArgs& a, hipStream_t s) {
+  const size_t lds = (size_t)a.max_population * sizeof(uint64_t);
+  const hipError_t e = allow_lds((const void*)finish_rank_batch_kernel, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(finish_rank_batch_kernel, dim3(a.n_rank_blocks), dim3(kRankThreads), lds, s,
+                     a);
+  return hipGetLastError();
+}
+
+// Genetic-step waves of every run in one launch; also re-arms the fitness
+// work queue for the next generation.
+__global__ __launch_bounds__(256) void ga_next_batch_kernel(BatchArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.counter = 0;
+  const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (gw >= a.n_ga_waves) return;
+  const int r = a.ga_wave_run[gw];
+  const BatchRun& run = a.runs[r];
+  GAArgs g{};
+  g.pop_a = run.pop0;
+  g.pop_b = run.pop1;
+  g.out_a = run.pop0;
+  g.out_b = run.pop1;
+  g.fitness = run.fit32;
+  g.order = run.order;
+  g.gen_ptr = &run.state->gen;
+  g.stop = &run.state->stop;
+  g.P = run.P;
+  g.K = run.K;
+  g.k = run.k;
+  g.E = run.E;
+  g.elite_mode = run.elite_mode;
+  g.thr_cross = run.thr_cross;
+  g.thr_mut = run.thr_mut;
+  g.sigma = run.sigma;
+  g.seed = run.seed;
+  ga_next_wave(g, gw - run.ga_wave0);
+}
+
+hipError_t launch_ga_next_batch(const BatchArgs& a, hipStream_t s) {
+  const int blocks = (a.n_ga_waves + 3) / 4;
+  hipLaunchKernelGGL(ga_next_batch_kernel, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void batch_reset_kernel(BatchArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.counter = 0;
+}
+
+hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- surrogate
+// Parameters: W1 [H x n_in], b1 [H], W2 [H x H], b2 [H], w3 [H], b3 [1] in
+// one flat vector.  Weight element e of tensor t is
+// float32(2u - 1) * float32(1 / sqrt(fan_in)) with u = (lo32(o0) >> 8) 2^-24
+// from key (seed, 3), counter (0, t, e, 0); biases start at zero.
+__global__ void mlp_init_kernel(float* params, int n_in, int H, uint64_t seed) {
+  const int64_t o1 = (int64_t)H * n_in, o2 = o1 + H, o3 = o2 + (int64_t)H * H, o4 = o3 + H,
+                o5 = o4 + H, total = o5 + 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  int tensor;
+  int64_t e;
+  int fan;
+  if (i < o1) { tensor = 0; e = i; fan = n_in; }
+  else if (i < o2) { params[i] = 0.f; return; }
+  else if (i < o3) { tensor = 2; e = i - o2; fan = H; }
+  else if (i < o4) { params[i] = 0.f; return; }
+  else if (i < o5) { tensor = 4; e = i - o4; fan = H; }
+  else { params[i] = 0.f; return; }
+  const U64x4 b = draw(seed, 3, 0, (uint64_t)tensor, (uint64_t)e);
+  const int32_t k = (int32_t)((uint32_t)(b.o0 & 0xFFFFFFFFull) >> 8);
+  const float u2 = (float)(2 * k - (1 << 24)) * 0x1p-24f;       // 2u - 1, exact
+  const float scale = (float)(1.0 / sqrt((double)fan));
+  params[i] = __fmul_rn(u2, scale);
+}
+
+hipError_t launch_mlp_init(float* params, int n_in, int H, uint64_t seed, hipStream_t s) {
+  const int64_t total = (int64_t)H * n_in + H + (int64_t)H * H + H + H + 1;
+  hipLaunchKernelGGL(mlp_init_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     params, n_in, H, seed);
+  return hipGetLastError();
+}
+
+// Appends the generation just evaluated (genes and log error, the error
+// clamped to [1e-30, 1e30]) at the archive's ring position.  Skipped when
+// the generation's fitness launch did not run (the run had stopped).
+__global__ void archive_append_kernel(ArchiveArgs a) {
+  if (a.run->stop_seen) return;
+  const int ev = a.run->evaluated;
+  const float* pop = (ev & 1) ? a.pop1 : a.pop0;
+  const int head = a.st->head;
+  const int64_t n = (int64_t)a.P * a.K;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i / a.K), g = (int)(i - (int64_t)c * a.K);
+    const int row = (head + c) % a.capacity;
+    a.genes[(int64_t)row * a.K + g] = pop[i];
+    if (g == 0) {
+      double f = a.fit64[c];
+      f = isnan(f) ? 1e30 : fmin(fmax(f, 1e-30), 1e30);
+      a.target[row] = (float)log(f);
+    }
+  }
+}
+
+hipError_t launch_archive_append(const ArchiveArgs& a, hipStream_t s) {
+  const int64_t n = (int64_t)a.P * a.K;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(archive_append_kernel, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// Advances the archive ring after an append and recomputes the mean and
+// inverse standard deviation of its targets (fixed-order float64 sums).
+__global__ __launch_bounds__(1024) void archive_stats_kernel(const float* target, SurrogateState* st,
+                                                             const RunState* run, int P,
+                                                             int capacity) {
+  __shared__ double s1[1024], s2[1024];
+  __shared__ int cnt;
+  if (run->stop_seen) return;
+  if (threadIdx.x == 0) {
+    const int c = min(st->count + P, capacity);
+    st->count = c;
+    st->head = (st->head + P) % capacity;
+    cnt = c;
+  }
+  __syncthreads();
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const double v = target[i];
+    a += v;
+    b += v * v;
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int k = 512; k > 0; k >>= 1) {
+    if (threadIdx.x < k) {
+      s1[threadIdx.x] += s1[threadIdx.x + k];
+      s2[threadIdx.x] += s2[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mean = s1[0] / cnt;
+    const double var = fmax(s2[0] / cnt - mean * mean, 1e-12);
+    st->mean = (float)mean;
+    st->inv_std = (float)(1.0 / sqrt(var));
+  }
+}
+
+hipError_t launch_archive_stats(const float* target, SurrogateState* st, const RunState* run,
+                                int P, int capacity, hipStream_t s) {
+  hipLaunchKernelGGL(archive_stats_kernel, dim3(1), dim3(1024), 0, s, target, st, run, P,
+                     capacity);
+  return hipGetLastError();
+}
+
+// Minibatch of B archive rows drawn with replacement: row b is
+// (u32 * count) >> 32 with u32 = lo32(o0) of key (seed, 3), counter
+// (generation, 1 + step, b, 0); targets standardised.
+__global__ void sample_minibatch_kernel(const float* genes, const float* target, int K,
+                                        const SurrogateState* st, const RunState* run,
+                                        uint64_t seed, int step, int B, float* Xb, float* tb) {
+  if (run->stop) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * K) return;
+  const int b = (int)(i / K), g = (int)(i - (int64_t)b * K);
+  const U64x4 r = draw(seed, 3, (uint64_t)run->evaluated, (uint64_t)(1 + step), (uint64_t)b);
+  const int idx = (int)(((r.o0 & 0xFFFFFFFFull) * (uint64_t)st->count) >> 32);
+  Xb[i] = genes[(int64_t)idx * K + g];
+  if (g == 0) tb[b] = (target[idx] - st->mean) * st->inv_std;
+}
+
+hipError_t launch_sample_minibatch(const float* genes, const float* target, int32_t K,
+                                   const SurrogateState* st, const RunState* run, uint64_t seed,
+                                   int32_t step, int32_t B, float* Xb, float* tb, hipStream_t s) {
+  const int64_t n = (int64_t)B * K;
+  hipLaunchKernelGGL(sample_minibatch_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     genes, target, K, st, run, seed, step, B, Xb, tb);
+  return hipGetLastError();
+}
+
+// Audit sample: A candidates drawn uniformly with replacement (key
+// (seed, 3), counter (generation, 0x7FFFFFFF, a, 0)); their genes and
+// predictions are copied out for exact scoring.
+__global__ void audit_pick_kernel(const float* cand, const float* pred, int C, int K,
+                                  const RunState* run, uint64_t seed, int A, float* genes,
+                                  float* pred_out) {
+  if (run->stop) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)A * K) return;
+  const int a = (int)(i / K), g = (int)(i - (int64_t)a * K);
+  const U64x4 r = draw(seed, 3, (uint64_t)run->gen, 0x7FFFFFFFull, (uint64_t)a);
+  const int idx = (int)(((r.o0 & 0xFFFFFFFFull) * (uint64_t)C) >> 32);
+  genes[i] = cand[(int64_t)idx * K + g];
+  if (g == 0) pred_out[a] = pred[idx];
+}
+
+hipError_t launch_audit_pick(const float* cand, const float* pred, int32_t C, int32_t K,
+                             const RunState* run, uint64_t seed, int32_t A, float* genes,
+                             float* pred_out, hipStream_t s) {
+  const int64_t n = (int64_t)A * K;
+  hipLaunchKernelGGL(audit_pick_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cand,
+                     pred, C, K, run, seed, A, genes, pred_out);
+  return hipGetLastError();
+}
+
+// Spearman correlation of the audit's predicted and exact errors (ranks by
+// (value, index), Pearson of the ranks), and the screening decision: the
+// offspring are screened only when the archive is large enough and the
+// correlation reaches rho_min; otherwise the plain offspring are kept.
+__global__ __launch_bounds__(1024) void spearman_gate_kernel(const float* pred, const float* exact,
+                                                             int A, float rho_min, int min_archive,
+                                                             const RunState* run,
+                                                             SurrogateState* st) {
+  __shared__ float ra[1024], rb[1024];
+  __shared__ double sab[1024], saa[1024], sbb[1024];
+  if (run->stop) return;
+  const int i = threadIdx.x;
+  if (i < A) {
+    const float p = rank_key_value(pred[i]), e = rank_key_value(exact[i]);
+    int cp = 0, ce = 0;
+    for (int j = 0; j < A; ++j) {
+      const float pj = rank_key_value(pred[j]), ej = rank_key_value(exact[j]);
+      cp += (pj < p || (pj == p && j < i)) ? 1 : 0;
+      ce += (ej < e || (ej == e && j < i)) ? 1 : 0;
+    }
+    ra[i] = (float)cp;
+    rb[i] = (float)ce;
+  }
+  __syncthreads();
+  const double mean = 0.5 * (A - 1);
+  const double a = i < A ? ra[i] - mean : 0.0, b = i < A ? rb[i] - mean : 0.0;
+  sab[i] = a * b;
+  saa[i] = a * a;
+  sbb[i] = b * b;
+  __syncthreads();
+  for (int k = 512; k > 0; k >>= 1) {
+    if (i < k) {
+      sab[i] += sab[i + k];
+      saa[i] += saa[i + k];
+      sbb[i] += sbb[i + k];
+    }
+    __syncthreads();
+  }
+  if (i == 0) {
+    const double den = sqrt(saa[0] * sbb[0]);
+    const float rho = den > 0 ? (float)(sab[0] / den) : 0.f;
+    st->rho = rho;
+    const int use = (st->count >= min_archive && rho >= rho_min) ? 1 : 0;
+    st->use = use;
+    st->screened += use;
+  }
+}
+
+hipError_t launch_spearman_gate(const float* pred, const float* exact, int32_t A, float rho_min,
+                                int32_t min_archive, const RunState* run, SurrogateState* st,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(spearman_gate_kernel, dim3(1), dim3(1024), 0, s, pred, exact, A, rho_min,
+                     min_archive, run, st);
+  return hipGetLastError();
+}
+
+// Rank of every value by (value, index) for up to a few hundred thousand
+// values: each workgroup ranks 64 of them against all keys, staged through
+// LDS 4096 at a time and counted by 16 waves.
+constexpr int kLargeChunk = 4096;
+__global__ __launch_bounds__(1024) void rank_large_kernel(const float* v, int n, int32_t* rank,
+                                                          const RunState* run) {
+  __shared__ uint64_t keys[kLargeChunk];
+  __shared__ uint32_t cnt[1024];
+  if (run && run->stop) return;
+  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int part = threadIdx.x >> 6;                      // 16 parts
+  const uint64_t ke = e < n ? rank_key(v[e], e) : ~0ull;
+  uint32_t c = 0;
+  for (int c0 = 0; c0 < n; c0 += kLargeChunk) {
+    const int m = min(kLargeChunk, n - c0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += blockDim.x) keys[j] = rank_key(v[c0 + j], c0 + j);
+    __syncthreads();
+    const int per = (m + 15) / 16;
+    const int j0 = part * per, j1 = min(j0 + per, m);
+    for (int j = j0; j < j1; ++j) c += keys[j] < ke ? 1u : 0u;
+  }
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x < 64 && e < n) {
+    uint32_t t = 0;
+    for (int k = 0; k < 16; ++k) t += cnt[k * 64 + threadIdx.x];
+    rank[e] = (int32_t)t;
+  }
+}
+
+hipError_t launch_rank_large(const float* v, int32_t n, int32_t* rank, const RunState* run,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(rank_large_kernel, dim3((n + 63) / 64), dim3(1024), 0, s, v, n, rank, run);
+  return hipGetLastError();
+}
+
+// Next population's offspring slots: with screening, candidate i goes to
+// slot E + rank_i when its predicted rank is below P - E; without, the
+// first P - E candidates (the plain offspring) go to slots E..P-1.
+__global__ void gather_next_kernel(const float* cand, const int32_t* rank, int C, int K, int E,
+                                   int P, const RunState* run, const SurrogateState* st,
+                                   float* pop0, float* pop1) {
+  if (run->stop) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)C * K) return;
+  const int c = (int)(i / K), g = (int)(i - (int64_t)c * K);
+  int slot = -1;
+  if (st->use) {
+    if (rank[c] < P - E) slot = E + rank[c];
+  } else if (c < P - E) {
+    slot = E + c;
+  }
+  if (slot < 0) return;
+  float* pop = (run->gen & 1) ? pop1 : pop0;
+  pop[(int64_t)slot * K + g] = cand[i];
+}
+
+hipError_t launch_gather_next(const float* cand, const int32_t* rank, int32_t C, int32_t K,
+                              int32_t E, int32_t P, const RunState* run, const SurrogateState* st,
+                              float* pop0, float* pop1, hipStream_t s) {
+  const int64_t n = (int64_t)C * K;
+  hipLaunchKernelGGL(gather_next_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cand,
+                     rank, C, K, E, P, run, st, pop0, pop1);
   return hipGetLastError();
 }
 

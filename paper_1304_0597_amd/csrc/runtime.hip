@@ -7,7 +7,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "../../include/game.h"
 #include "common.h"
@@ -65,8 +67,8 @@ int check_config(const game_config* c, int32_t n_features) {
     return fail(GAME_EINVAL, "init_mode %d not in 0..2", c->init_mode);
   if (c->error_fn < 0 || c->error_fn > 3)
     return fail(GAME_EINVAL, "error_fn %d not in 0..3", c->error_fn);
-  if (c->precision != GAME_FP32)
-    return fail(GAME_EINVAL, "precision %d is not available in this build", c->precision);
+  if (c->precision != GAME_FP32 && c->precision != GAME_BF16)
+    return fail(GAME_EINVAL, "precision %d not 0 (FP32) or 1 (BF16)", c->precision);
   if (!(c->p_crossover >= 0.f && c->p_crossover <= 1.f))
     return fail(GAME_EINVAL, "p_crossover not in [0, 1]");
   if (!(c->p_mutation >= 0.f && c->p_mutation <= 1.f))
@@ -85,13 +87,13 @@ int check_config(const game_config* c, int32_t n_features) {
 }
 
 struct Layout {
-  size_t state, pop0, pop1, fit32, fit64, order, partial, total;
+  size_t state, pop0, pop1, fit32, fit64, order, partial, rescore, total;
 };
 
 Layout layout(const game_config* c, int32_t n_features) {
   const size_t P = (size_t)c->population;
   const size_t K = (size_t)genes_of(c, n_features);
-  const size_t Ppad = (P + kTileCols - 1) / kTileCols * kTileCols;
+  const size_t Ppad = (P + kMaxTileCols - 1) / kMaxTileCols * kMaxTileCols;
   Layout L{};
   size_t off = 0;
   L.state = off; off += align_up(sizeof(RunState));
@@ -101,6 +103,7 @@ Layout layout(const game_config* c, int32_t n_features) {
   L.fit64 = off; off += align_up(P * sizeof(double));
   L.order = off; off += align_up(P * sizeof(int32_t));
   L.partial = off; off += align_up(Ppad * kMaxSplits * sizeof(double));
+  L.rescore = off; off += align_up(64 * sizeof(double));
   L.total = off;
   return L;
 }
@@ -124,9 +127,35 @@ struct game_ctx {
   double* fit64;
   int32_t* order;
   double* partial;
+  double* rescore;          // float64 error of the last re-scored elite
   bool initialized;
   hipGraphExec_t graph;
   int graph_steps;
+  game_surrogate_ctx* sur;  // attached fitness surrogate (screening), or null
+};
+
+struct game_surrogate_ctx {
+  game_surrogate_config cfg;
+  int32_t n_in;
+  int32_t H;
+  int32_t max_batch;
+  int64_t n_params;
+  hipStream_t stream;
+  float* params;
+  float* grads;
+  float* m;
+  float* v;
+  SurrogateState* st;
+  // training minibatch
+  float *Xb, *tb, *Z1, *H1, *Z2, *H2, *y, *dy, *dZ2, *dZ1;
+  // predictions over up to max_batch rows
+  float *H1c, *H2c, *yc;
+  // archive of exact evaluations
+  float *arch_genes, *arch_target;
+  // screening
+  float* cand;
+  int32_t* rank;
+  float *audit_genes, *audit_pred, *audit_exact;
 };
 
 namespace {
@@ -144,8 +173,37 @@ FitArgs fit_args(const game_ctx* h, const float* X, const float* t, int64_t NP, 
   a.partial = h->partial;
   a.error_fn = h->cfg.error_fn;
   a.R = h->cfg.tmse_R;
-  plan_fitness(a, h->cfg.degree, h->cfg.basis);
+  if (h->cfg.precision == GAME_BF16) plan_fitness_bf16(a, h->cfg.degree, h->cfg.basis);
+  else plan_fitness(a, h->cfg.degree, h->cfg.basis);
   return a;
+}
+
+hipError_t launch_fitness(const game_ctx* h, const FitArgs& a, hipStream_t s) {
+  if (h->cfg.precision == GAME_BF16) return launch_fitness_bf16(a, h->cfg.basis, h->cfg.degree, s);
+  return launch_fitness_f32(a, h->cfg.basis, h->cfg.degree, s);
+}
+
+// Float64 error of n chromosomes over (X, t); partials use the workspace.
+hipError_t rescore64(const game_ctx* h, const float* X, const float* t, int64_t NP,
+                     const float* genes, int32_t n, double* out, hipStream_t s) {
+  Rescore64Args r{};
+  r.X = X;
+  r.t = t;
+  r.genes = genes;
+  r.partial = h->partial;
+  r.NP = NP;
+  r.N = h->N;
+  r.K = h->K;
+  r.n = n;
+  int64_t blocks = (NP + 255) / 256;
+  const int64_t cap = (int64_t)kMaxSplits * kMaxTileCols / (n < 1 ? 1 : n);
+  if (blocks > 256) blocks = 256;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  r.blocks = (int32_t)blocks;
+  r.error_fn = h->cfg.error_fn;
+  r.R = h->cfg.tmse_R;
+  return launch_rescore64(r, h->cfg.basis, h->cfg.degree, out, s);
 }
 
 GAArgs ga_args(const game_config* c, int32_t K) {
@@ -164,6 +222,192 @@ GAArgs ga_args(const game_config* c, int32_t K) {
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// ----------------------------------------------------------- surrogate
+struct SurLayout {
+  size_t st, params, grads, m, v, Xb, tb, Z1, H1, Z2, H2, y, dy, dZ2, dZ1, H1c, H2c, yc, ag, at,
+      cand, rank, aug, aup, aue, total;
+  int64_t n_params;
+};
+
+SurLayout sur_layout(const game_surrogate_config* c, int32_t n_in, int32_t max_batch) {
+  SurLayout L{};
+  const size_t H = c->hidden, B = c->minibatch, C = max_batch, A = c->audit;
+  L.n_params = (int64_t)H * n_in + H + (int64_t)H * H + H + H + 1;
+  const size_t P = (size_t)L.n_params * sizeof(float);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += align_up(bytes); return o; };
+  L.st = take(sizeof(SurrogateState));
+  L.params = take(P);
+  L.grads = take(P);
+  L.m = take(P);
+  L.v = take(P);
+  L.Xb = take(B * n_in * 4);
+  L.tb = take(B * 4);
+  L.Z1 = take(B * H * 4);
+  L.H1 = take(B * H * 4);
+  L.Z2 = take(B * H * 4);
+  L.H2 = take(B * H * 4);
+  L.y = take(B * 4);
+  L.dy = take(B * 4);
+  L.dZ2 = take(B * H * 4);
+  L.dZ1 = take(B * H * 4);
+  L.H1c = take(C * H * 4);
+  L.H2c = take(C * H * 4);
+  L.yc = take(C * 4);
+  L.ag = take((size_t)c->archive * n_in * 4);
+  L.at = take((size_t)c->archive * 4);
+  L.cand = take(C * n_in * 4);
+  L.rank = take(C * 4);
+  L.aug = take(A * n_in * 4);
+  L.aup = take(A * 4);
+  L.aue = take(A * 4);
+  L.total = off;
+  return L;
+}
+
+int check_surrogate(const game_surrogate_config* c, int32_t n_in, int32_t max_batch) {
+  if (!c) return fail(GAME_EINVAL, "surrogate config is NULL");
+  if (c->hidden < 1 || c->hidden > 4096) return fail(GAME_EINVAL, "hidden not in 1..4096");
+  if (c->archive < 1) return fail(GAME_EINVAL, "archive < 1");
+  if (c->minibatch < 1 || c->minibatch > (1 << 20)) return fail(GAME_EINVAL, "minibatch out of range");
+  if (c->train_steps < 0 || c->train_steps > 1024) return fail(GAME_EINVAL, "train_steps out of range");
+  if (!(c->lr >= 0.f)) return fail(GAME_EINVAL, "lr < 0");
+  if (c->oversample < 1 || c->oversample > 64) return fail(GAME_EINVAL, "oversample not in 1..64");
+  if (c->audit < 2 || c->audit > 1024) return fail(GAME_EINVAL, "audit not in 2..1024");
+  if (n_in < 1 || n_in > kMaxGenes) return fail(GAME_EINVAL, "n_genes out of range");
+  if (max_batch < 1) return fail(GAME_EINVAL, "max_batch < 1");
+  return GAME_OK;
+}
+
+GemmArgs gemm(const float* A, int64_t lda_m, int64_t lda_k, const float* B, int64_t ldb_n,
+              int64_t ldb_k, float* C, int64_t ldc, int M, int N, int K, const float* bias, int act,
+              float* Z, const float* aux, int64_t ld_aux, const int32_t* skip) {
+  GemmArgs g{};
+  g.A = A; g.lda_m = lda_m; g.lda_k = lda_k;
+  g.B = B; g.ldb_n = ldb_n; g.ldb_k = ldb_k;
+  g.C = C; g.ldc = ldc; g.M = M; g.N = N; g.K = K;
+  g.bias = bias; g.act = act; g.Z = Z; g.aux = aux; g.ld_aux = ld_aux; g.skip = skip;
+  return g;
+}
+
+struct SurParams {
+  float *W1, *b1, *W2, *b2, *w3, *b3;
+};
+
+SurParams split_params(const game_surrogate_ctx* s, float* base) {
+  const int64_t H = s->H, n = s->n_in;
+  SurParams p{};
+  p.W1 = base;
+  p.b1 = p.W1 + H * n;
+  p.W2 = p.b1 + H;
+  p.b2 = p.W2 + H * H;
+  p.w3 = p.b2 + H;
+  p.b3 = p.w3 + H;
+  return p;
+}
+
+// Forward over n rows of X [n x n_in]; stores Z1/Z2 when given (training).
+int sur_forward(game_surrogate_ctx* s, const float* X, int n, float* Z1, float* H1, float* Z2,
+                float* H2, float* y, const int32_t* skip, hipStream_t st) {
+  const bool bf16 = !s->cfg.fp32_operands;
+  const SurParams p = split_params(s, s->params);
+  const int H = s->H, ni = s->n_in;
+  GAME_HIP(launch_gemm(gemm(X, ni, 1, p.W1, ni, 1, H1, H, n, H, ni, p.b1, 1, Z1, nullptr, 0, skip),
+                       bf16, st));
+  GAME_HIP(launch_gemm(gemm(H1, H, 1, p.W2, H, 1, H2, H, n, H, H, p.b2, 1, Z2, nullptr, 0, skip),
+                       bf16, st));
+  GAME_HIP(launch_gemm(gemm(H2, H, 1, p.w3, H, 1, y, 1, n, 1, H, p.b3, 0, nullptr, nullptr, 0, skip),
+                       bf16, st));
+  return GAME_OK;
+}
+
+// Gradients of mean((y - t)^2) over the n rows in s->Xb / s->tb into s->grads.
+int sur_gradients(game_surrogate_ctx* s, int n, const int32_t* skip, hipStream_t st) {
+  const bool bf16 = !s->cfg.fp32_operands;
+  const int H = s->H, ni = s->n_in;
+  int rc = sur_forward(s, s->Xb, n, s->Z1, s->H1, s->Z2, s->H2, s->y, skip, st);
+  if (rc) return rc;
+  const SurParams p = split_params(s, s->params);
+  const SurParams g = split_params(s, s->grads);
+  GAME_HIP(launch_out_grad(s->y, s->tb, n, p.w3, s->Z2, H, s->dy, s->dZ2, skip, st));
+  // dw3 = dy^T H2, db3 = sum dy
+  GAME_HIP(launch_gemm(gemm(s->dy, 0, 1, s->H2, 1, H, g.w3, H, 1, H, n, nullptr, 0, nullptr,
+                            nullptr, 0, skip), bf16, st));
+  GAME_HIP(launch_colsum(s->dy, n, 1, 1, g.b3, skip, st));
+  // dW2 = dZ2^T H1, db2 = colsum dZ2
+  GAME_HIP(launch_gemm(gemm(s->dZ2, 1, H, s->H1, 1, H, g.W2, H, H, H, n, nullptr, 0, nullptr,
+                            nullptr, 0, skip), bf16, st));
+  GAME_HIP(launch_colsum(s->dZ2, n, H, H, g.b2, skip, st));
+  // dZ1 = (dZ2 W2) * gelu'(Z1)
+  GAME_HIP(launch_gemm(gemm(s->dZ2, H, 1, p.W2, 1, H, s->dZ1, H, n, H, H, nullptr, 2, nullptr,
+                            s->Z1, H, skip), bf16, st));
+  // dW1 = dZ1^T X, db1 = colsum dZ1
+  GAME_HIP(launch_gemm(gemm(s->dZ1, 1, H, s->Xb, 1, ni, g.W1, ni, H, ni, n, nullptr, 0, nullptr,
+                            nullptr, 0, skip), bf16, st));
+  GAME_HIP(launch_colsum(s->dZ1, n, H, H, g.b1, skip, st));
+  return GAME_OK;
+}
+
+// Screened generation tail (after the evaluation of the current population):
+// archive it, train, generate oversampled offspring, score them with the
+// network, audit a random sample exactly, and fill the next population with
+// the best-predicted offspring (or the plain offspring when the audit's rank
+// correlation is too low).
+int enqueue_screening(game_ctx* h, hipStream_t s) {
+  game_surrogate_ctx* sr = h->sur;
+  const game_surrogate_config& c = sr->cfg;
+  const int32_t* stop = &h->state->stop;
+  const int P = h->cfg.population, E = h->cfg.elitism, K = h->K;
+  ArchiveArgs aa{};
+  aa.run = h->state;
+  aa.pop0 = h->pop[0];
+  aa.pop1 = h->pop[1];
+  aa.fit64 = h->fit64;
+  aa.P = P;
+  aa.K = K;
+  aa.genes = sr->arch_genes;
+  aa.target = sr->arch_target;
+  aa.capacity = c.archive;
+  aa.st = sr->st;
+  GAME_HIP(launch_archive_append(aa, s));
+  GAME_HIP(launch_archive_stats(sr->arch_target, sr->st, h->state, P, c.archive, s));
+  for (int step = 0; step < c.train_steps; ++step) {
+    GAME_HIP(launch_sample_minibatch(sr->arch_genes, sr->arch_target, K, sr->st, h->state, c.seed,
+                                     step, c.minibatch, sr->Xb, sr->tb, s));
+    int rc = sur_gradients(sr, c.minibatch, stop, s);
+    if (rc) return rc;
+    GAME_HIP(launch_adam(sr->params, sr->grads, sr->m, sr->v, sr->n_params, c.lr, sr->st, stop, s));
+  }
+  const int C = c.oversample * (P - E);
+  GAArgs ga = ga_args(&h->cfg, K);
+  ga.pop_a = h->pop[0];
+  ga.pop_b = h->pop[1];
+  ga.out_a = h->pop[0];
+  ga.out_b = h->pop[1];
+  ga.fitness = h->fit32;
+  ga.order = h->order;
+  ga.gen_ptr = &h->state->gen;
+  ga.stop = stop;
+  ga.n_slots = E + C;
+  ga.children = sr->cand;
+  GAME_HIP(launch_ga_next(ga, s));
+  int rc = sur_forward(sr, sr->cand, C, nullptr, sr->H1c, nullptr, sr->H2c, sr->yc, stop, s);
+  if (rc) return rc;
+  GAME_HIP(launch_audit_pick(sr->cand, sr->yc, C, K, h->state, c.seed, c.audit, sr->audit_genes,
+                             sr->audit_pred, s));
+  FitArgs fa = fit_args(h, h->X, h->t, h->NP, sr->audit_genes, c.audit);
+  fa.stop = stop;
+  GAME_HIP(launch_fitness(h, fa, s));
+  GAME_HIP(launch_finish(h->partial, fa.ld_partial, c.audit, fa.n_splits, h->NP, h->cfg.error_fn,
+                         sr->audit_exact, nullptr, s));
+  GAME_HIP(launch_spearman_gate(sr->audit_pred, sr->audit_exact, c.audit, c.rho_min,
+                                c.min_archive, h->state, sr->st, s));
+  GAME_HIP(launch_rank_large(sr->yc, C, sr->rank, h->state, s));
+  GAME_HIP(launch_gather_next(sr->cand, sr->rank, C, K, E, P, h->state, sr->st, h->pop[0],
+                              h->pop[1], s));
+  return GAME_OK;
+}
+
 // One generation of the loop on stream s: evaluate pop[gen & 1], finish and
 // rank, stop test, then build pop[(gen + 1) & 1].
 int enqueue_step(game_ctx* h, hipStream_t s) {
@@ -172,7 +416,7 @@ int enqueue_step(game_ctx* h, hipStream_t s) {
   fa.gen_sel = &h->state->gen;
   fa.stop = &h->state->stop;
   fa.stop_seen = &h->state->stop_seen;
-  GAME_HIP(launch_fitness_f32(fa, h->cfg.basis, h->cfg.degree, s));
+  GAME_HIP(launch_fitness(h, fa, s));
   RankArgs ra{};
   ra.partial = h->partial;
   ra.n_splits = fa.n_splits;
@@ -185,6 +429,7 @@ int enqueue_step(game_ctx* h, hipStream_t s) {
   ra.order = h->order;
   ra.state = h->state;
   GAME_HIP(launch_finish_rank(ra, s));
+  if (h->sur) return enqueue_screening(h, s);
   GAArgs ga = ga_args(&h->cfg, h->K);
   ga.pop_a = h->pop[0];
   ga.pop_b = h->pop[1];
@@ -278,6 +523,7 @@ int game_create(const game_config* c, const float* X, const float* t, int64_t NP
   h->fit64 = (double*)(base + L.fit64);
   h->order = (int32_t*)(base + L.order);
   h->partial = (double*)(base + L.partial);
+  h->rescore = (double*)(base + L.rescore);
   hipError_t e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete h;
@@ -307,7 +553,7 @@ int game_fitness(game_t h, const float* genes, int32_t n, float* f32, double* f6
   if (n < 1 || n > h->cfg.population)
     return fail(GAME_EINVAL, "n %d not in 1..population (%d)", n, h->cfg.population);
   FitArgs fa = fit_args(h, h->X, h->t, h->NP, genes, n);
-  GAME_HIP(launch_fitness_f32(fa, h->cfg.basis, h->cfg.degree, h->stream));
+  GAME_HIP(launch_fitness(h, fa, h->stream));
   GAME_HIP(launch_finish(h->partial, fa.ld_partial, n, fa.n_splits, h->NP, h->cfg.error_fn, f32, f64, h->stream));
   return GAME_OK;
 }
@@ -322,9 +568,28 @@ int game_evaluate(game_t h, const float* X, const float* t, int64_t NP, const fl
   if (n < 1 || n > h->cfg.population)
     return fail(GAME_EINVAL, "n %d not in 1..population (%d)", n, h->cfg.population);
   FitArgs fa = fit_args(h, X, t, NP, genes, n);
-  GAME_HIP(launch_fitness_f32(fa, h->cfg.basis, h->cfg.degree, h->stream));
+  GAME_HIP(launch_fitness(h, fa, h->stream));
   GAME_HIP(launch_finish(h->partial, fa.ld_partial, n, fa.n_splits, NP, h->cfg.error_fn, nullptr, err64,
                          h->stream));
+  return GAME_OK;
+}
+
+int game_rescore64(game_t h, const float* X, const float* t, int64_t NP, const float* genes,
+                   int32_t n, double* err64) {
+  if (!h) return fail(GAME_EINVAL, "handle is NULL");
+  if (!genes || !err64) return fail(GAME_EINVAL, "NULL argument");
+  if ((X == nullptr) != (t == nullptr)) return fail(GAME_EINVAL, "X and t must both be set or NULL");
+  if (!X) {
+    X = h->X;
+    t = h->t;
+    NP = h->NP;
+  }
+  if (NP < 1) return fail(GAME_EINVAL, "n_patterns < 1");
+  if (n < 1 || n > kMaxTileCols * kMaxSplits)
+    return fail(GAME_EINVAL, "n %d not in 1..%d", n, kMaxTileCols * kMaxSplits);
+  if (n > h->cfg.population)
+    return fail(GAME_EINVAL, "n %d not in 1..population (%d)", n, h->cfg.population);
+  GAME_HIP(rescore64(h, X, t, NP, genes, n, err64, h->stream));
   return GAME_OK;
 }
 
@@ -385,6 +650,15 @@ int game_run(game_t h, int32_t max_gen, double target, int32_t* gens_done, float
   GAME_HIP(hipStreamSynchronize(h->stream));
   if (gens_done) *gens_done = st.gen;
   if (best_err) *best_err = st.best_err;
+  if (st.best >= 0 && h->cfg.precision != GAME_FP32) {
+    // Reduced-precision run: the elite's reported error is its float64 re-score.
+    const float* src = h->pop[st.gen & 1] + (int64_t)st.best * h->K;
+    GAME_HIP(rescore64(h, h->X, h->t, h->NP, src, 1, h->rescore, h->stream));
+    double v = 0.0;
+    GAME_HIP(hipMemcpyAsync(&v, h->rescore, sizeof v, hipMemcpyDeviceToHost, h->stream));
+    GAME_HIP(hipStreamSynchronize(h->stream));
+    if (best_err) *best_err = v;
+  }
   if (best_genes && st.best >= 0) {
     const float* src = h->pop[st.gen & 1] + (int64_t)st.best * h->K;
     GAME_HIP(hipMemcpyAsync(best_genes, src, sizeof(float) * h->K, hipMemcpyDeviceToHost,
@@ -485,6 +759,605 @@ int game_init_genes(const game_config* c, int32_t K, float* out, void* stream) {
   if (K < 1 || K > kMaxGenes) return fail(GAME_EINVAL, "n_genes %d not in 1..%d", K, kMaxGenes);
   if (c->init_mode < 0 || c->init_mode > 2) return fail(GAME_EINVAL, "init_mode not in 0..2");
   GAME_HIP(launch_init_genes(c->seed, c->init_mode, c->population, K, out, (hipStream_t)stream));
+  return GAME_OK;
+}
+
+// ---------------------------------------------------------------- surrogate
+int game_surrogate_config_default(game_surrogate_config* c) {
+  if (!c) return fail(GAME_EINVAL, "config is NULL");
+  memset(c, 0, sizeof *c);
+  c->hidden = 256;
+  c->fp32_operands = 0;
+  c->archive = 65536;
+  c->minibatch = 1024;
+  c->train_steps = 4;
+  c->lr = 1e-3f;
+  c->oversample = 8;
+  c->audit = 64;
+  c->rho_min = 0.8f;
+  c->min_archive = 4096;
+  c->seed = 0;
+  return GAME_OK;
+}
+
+size_t game_surrogate_workspace_size(const game_surrogate_config* c, int32_t n_genes,
+                                     int32_t max_batch) {
+  if (check_surrogate(c, n_genes, max_batch)) return 0;
+  return sur_layout(c, n_genes, max_batch).total;
+}
+
+int game_surrogate_create(const game_surrogate_config* c, int32_t n_genes, int32_t max_batch,
+                          void* ws, size_t ws_bytes, void* stream, game_surrogate_t* out) {
+  if (!out) return fail(GAME_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_surrogate(c, n_genes, max_batch);
+  if (rc) return rc;
+  if (!ws) return fail(GAME_EWORKSPACE, "workspace is NULL");
+  if (!aligned(ws, kAlign)) return fail(GAME_EWORKSPACE, "workspace not 256-byte aligned");
+  const SurLayout L = sur_layout(c, n_genes, max_batch);
+  if (ws_bytes < L.total)
+    return fail(GAME_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  char* b = (char*)ws;
+  game_surrogate_ctx* s = new game_surrogate_ctx{};
+  s->cfg = *c;
+  s->n_in = n_genes;
+  s->H = c->hidden;
+  s->max_batch = max_batch;
+  s->n_params = L.n_params;
+  s->stream = (hipStream_t)stream;
+  s->st = (SurrogateState*)(b + L.st);
+  s->params = (float*)(b + L.params);
+  s->grads = (float*)(b + L.grads);
+  s->m = (float*)(b + L.m);
+  s->v = (float*)(b + L.v);
+  s->Xb = (float*)(b + L.Xb);
+  s->tb = (float*)(b + L.tb);
+  s->Z1 = (float*)(b + L.Z1);
+  s->H1 = (float*)(b + L.H1);
+  s->Z2 = (float*)(b + L.Z2);
+  s->H2 = (float*)(b + L.H2);
+  s->y = (float*)(b + L.y);
+  s->dy = (float*)(b + L.dy);
+  s->dZ2 = (float*)(b + L.dZ2);
+  s->dZ1 = (float*)(b + L.dZ1);
+  s->H1c = (float*)(b + L.H1c);
+  s->H2c = (float*)(b + L.H2c);
+  s->yc = (float*)(b + L.yc);
+  s->arch_genes = (float*)(b + L.ag);
+  s->arch_target = (float*)(b + L.at);
+  s->cand = (float*)(b + L.cand);
+  s->rank = (int32_t*)(b + L.rank);
+  s->audit_genes = (float*)(b + L.aug);
+  s->audit_pred = (float*)(b + L.aup);
+  s->audit_exact = (float*)(b + L.aue);
+  hipError_t e = launch_fill_zero((float*)s->st, sizeof(SurrogateState) / sizeof(float), s->stream);
+  if (e == hipSuccess) e = launch_fill_zero(s->m, s->n_params, s->stream);
+  if (e == hipSuccess) e = launch_fill_zero(s->v, s->n_params, s->stream);
+  if (e == hipSuccess) e = launch_mlp_init(s->params, n_genes, s->H, c->seed, s->stream);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "surrogate init");
+  }
+  *out = s;
+  return GAME_OK;
+}
+
+int game_surrogate_destroy(game_surrogate_t s) {
+  if (!s) return fail(GAME_EINVAL, "surrogate is NULL");
+  delete s;
+  return GAME_OK;
+}
+
+int64_t game_surrogate_num_params(game_surrogate_t s) {
+  if (!s) return fail(GAME_EINVAL, "surrogate is NULL");
+  return s->n_params;
+}
+
+int game_surrogate_get_params(game_surrogate_t s, float* params) {
+  if (!s || !params) return fail(GAME_EINVAL, "NULL argument");
+  GAME_HIP(hipMemcpyAsync(params, s->params, sizeof(float) * s->n_params, hipMemcpyDeviceToDevice,
+                          s->stream));
+  return GAME_OK;
+}
+
+int game_surrogate_set_params(game_surrogate_t s, const float* params) {
+  if (!s || !params) return fail(GAME_EINVAL, "NULL argument");
+  GAME_HIP(hipMemcpyAsync(s->params, params, sizeof(float) * s->n_params, hipMemcpyDeviceToDevice,
+                          s->stream));
+  return GAME_OK;
+}
+
+int game_surrogate_predict(game_surrogate_t s, const float* genes, int32_t n, float* y) {
+  if (!s || !genes || !y) return fail(GAME_EINVAL, "NULL argument");
+  if (n < 1 || n > s->max_batch) return fail(GAME_EINVAL, "n %d not in 1..%d", n, s->max_batch);
+  int rc = sur_forward(s, genes, n, nullptr, s->H1c, nullptr, s->H2c, y, nullptr, s->stream);
+  return rc;
+}
+
+int game_surrogate_gradients(game_surrogate_t s, const float* genes, const float* target, int32_t n,
+                             float* grads, float* y) {
+  if (!s || !genes || !target || !grads) return fail(GAME_EINVAL, "NULL argument");
+  if (n < 1 || n > s->cfg.minibatch)
+    return fail(GAME_EINVAL, "n %d not in 1..minibatch (%d)", n, s->cfg.minibatch);
+  GAME_HIP(hipMemcpyAsync(s->Xb, genes, sizeof(float) * n * s->n_in, hipMemcpyDeviceToDevice,
+                          s->stream));
+  GAME_HIP(hipMemcpyAsync(s->tb, target, sizeof(float) * n, hipMemcpyDeviceToDevice, s->stream));
+  int rc = sur_gradients(s, n, nullptr, s->stream);
+  if (rc) return rc;
+  GAME_HIP(hipMemcpyAsync(grads, s->grads, sizeof(float) * s->n_params, hipMemcpyDeviceToDevice,
+                          s->stream));
+  if (y) GAME_HIP(hipMemcpyAsync(y, s->y, sizeof(float) * n, hipMemcpyDeviceToDevice, s->stream));
+  return GAME_OK;
+}
+
+int game_surrogate_train_step(game_surrogate_t s, const float* genes, const float* target,
+                              int32_t n) {
+  if (!s || !genes || !target) return fail(GAME_EINVAL, "NULL argument");
+  if (n < 1 || n > s->cfg.minibatch)
+    return fail(GAME_EINVAL, "n %d not in 1..minibatch (%d)", n, s->cfg.minibatch);
+  GAME_HIP(hipMemcpyAsync(s->Xb, genes, sizeof(float) * n * s->n_in, hipMemcpyDeviceToDevice,
+                          s->stream));
+  GAME_HIP(hipMemcpyAsync(s->tb, target, sizeof(float) * n, hipMemcpyDeviceToDevice, s->stream));
+  int rc = sur_gradients(s, n, nullptr, s->stream);
+  if (rc) return rc;
+  GAME_HIP(launch_adam(s->params, s->grads, s->m, s->v, s->n_params, s->cfg.lr, s->st, nullptr,
+                       s->stream));
+  return GAME_OK;
+}
+
+int game_attach_surrogate(game_t h, game_surrogate_t s) {
+  if (!h) return fail(GAME_EINVAL, "handle is NULL");
+  if (s) {
+    if (s->n_in != h->K)
+      return fail(GAME_EINVAL, "surrogate takes %d genes, the run has %d", s->n_in, h->K);
+    const int C = s->cfg.oversample * (h->cfg.population - h->cfg.elitism);
+    if (C > s->max_batch)
+      return fail(GAME_EINVAL, "oversampled offspring (%d) exceed max_batch (%d)", C, s->max_batch);
+    if (s->cfg.audit > h->cfg.population)
+      return fail(GAME_EINVAL, "audit (%d) exceeds the population", s->cfg.audit);
+    if (s->stream != h->stream) return fail(GAME_EINVAL, "surrogate and run use different streams");
+  }
+  h->sur = s;
+  if (h->graph) {
+    hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  return GAME_OK;
+}
+
+int game_surrogate_stats(game_surrogate_t s, float* rho, int32_t* use, int32_t* screened,
+                         int32_t* archive_count, int32_t* adam_steps) {
+  if (!s) return fail(GAME_EINVAL, "surrogate is NULL");
+  SurrogateState st{};
+  GAME_HIP(hipMemcpyAsync(&st, s->st, sizeof st, hipMemcpyDeviceToHost, s->stream));
+  GAME_HIP(hipStreamSynchronize(s->stream));
+  if (rho) *rho = st.rho;
+  if (use) *use = st.use;
+  if (screened) *screened = st.screened;
+  if (archive_count) *archive_count = st.count;
+  if (adam_steps) *adam_steps = st.step;
+  return GAME_OK;
+}
+
+// ------------------------------------------------------------------ batches
+}  // extern "C"
+
+struct game_batch_ctx {
+  int32_t n_runs;
+  std::vector<BatchRun> runs;
+  std::vector<game_config> cfgs;
+  BatchRun* runs_dev;
+  BatchItem* items_dev;
+  int32_t* counter;
+  int32_t* rank_block_run;
+  int32_t* ga_wave_run;
+  RunState* states;
+  int64_t item_capacity;
+  int32_t n_items;
+  int32_t n_rank_blocks;
+  int32_t n_ga_waves;
+  int32_t max_pop;
+  int32_t grid;
+  int32_t tiles_per_item;
+  int32_t max_gen;
+  size_t lds;
+  hipStream_t stream;
+  hipStream_t capture_stream;
+  hipGraphExec_t graph;
+  int graph_steps;
+  bool initialized;
+};
+
+namespace {
+
+struct BatchLayout {
+  size_t runs, items, counter, rank_map, ga_map, states, total;
+  std::vector<size_t> pop0, pop1, fit32, fit64, order, partial;
+  int64_t item_capacity;
+  int32_t n_rank_blocks, n_ga_waves;
+};
+
+int check_run(const game_run_desc& r, int i) {
+  const int rc = check_config(&r.cfg, r.n_features);
+  if (rc) {
+    const std::string msg = g_error;
+    return fail(rc, "run %d: %s", i, msg.c_str());
+  }
+  if (r.cfg.precision != GAME_FP32) return fail(GAME_EINVAL, "run %d: batches run in FP32", i);
+  if (r.n_patterns < 1) return fail(GAME_EINVAL, "run %d: n_patterns < 1", i);
+  if ((r.n_patterns + kTileRows - 1) / kTileRows > (int64_t)INT32_MAX)
+    return fail(GAME_EINVAL, "run %d: n_patterns too large", i);
+  return GAME_OK;
+}
+
+BatchLayout batch_layout(const game_run_desc* runs, int32_t n) {
+  BatchLayout L{};
+  int64_t cap = 0;
+  int32_t rb = 0, gw = 0;
+  for (int i = 0; i < n; ++i) {
+    const int P = runs[i].cfg.population;
+    cap += (int64_t)((P + kTileCols - 1) / kTileCols) * kMaxSplits;
+    rb += (P + kRankPerBlock - 1) / kRankPerBlock;
+    gw += runs[i].cfg.elitism + (P - runs[i].cfg.elitism + 1) / 2;
+  }
+  L.item_capacity = cap;
+  L.n_rank_blocks = rb;
+  L.n_ga_waves = gw;
+  size_t off = 0;
+  L.runs = off; off += align_up(sizeof(BatchRun) * n);
+  L.items = off; off += align_up(sizeof(BatchItem) * cap);
+  L.counter = off; off += align_up(sizeof(int32_t));
+  L.rank_map = off; off += align_up(sizeof(int32_t) * rb);
+  L.ga_map = off; off += align_up(sizeof(int32_t) * gw);
+  L.states = off; off += align_up(sizeof(RunState) * n);
+  for (int i = 0; i < n; ++i) {
+    const size_t P = runs[i].cfg.population;
+    const size_t K = (size_t)genes_of(&runs[i].cfg, runs[i].n_features);
+    const size_t Ppad = (P + kTileCols - 1) / kTileCols * kTileCols;
+    L.pop0.push_back(off); off += align_up(P * K * sizeof(float));
+    L.pop1.push_back(off); off += align_up(P * K * sizeof(float));
+    L.fit32.push_back(off); off += align_up(P * sizeof(float));
+    L.fit64.push_back(off); off += align_up(P * sizeof(double));
+    L.order.push_back(off); off += align_up(P * sizeof(int32_t));
+    L.partial.push_back(off); off += align_up(Ppad * kMaxSplits * sizeof(double));
+  }
+  L.total = off;
+  return L;
+}
+
+// Work decomposition: each run's patterns are cut into splits of about
+// `tiles` 256-row tiles; items are (run, chromosome tile, split), heaviest
+// first so the queue ends with small items.
+int build_items(game_batch_ctx* b, int32_t tiles) {
+  std::vector<BatchItem> items;
+  for (int r = 0; r < b->n_runs; ++r) {
+    BatchRun& run = b->runs[r];
+    int splits = (run.n_tiles + tiles - 1) / tiles;
+    if (splits > kMaxSplits) splits = kMaxSplits;
+    if (splits < 1) splits = 1;
+    run.tiles_per_split = (run.n_tiles + splits - 1) / splits;
+    run.n_splits = (run.n_tiles + run.tiles_per_split - 1) / run.tiles_per_split;
+    for (int c = 0; c < run.n_ctiles; ++c)
+      for (int sp = 0; sp < run.n_splits; ++sp) {
+        const int rows = std::min(run.tiles_per_split, run.n_tiles - sp * run.tiles_per_split);
+        items.push_back({r, c, sp, rows * run.Q * run.D});
+      }
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const BatchItem& x, const BatchItem& y) { return x.cost > y.cost; });
+  if ((int64_t)items.size() > b->item_capacity) return fail(GAME_EINVAL, "too many items");
+  GAME_HIP(hipMemcpyAsync(b->items_dev, items.data(), sizeof(BatchItem) * items.size(),
+                          hipMemcpyHostToDevice, b->stream));
+  GAME_HIP(hipMemcpyAsync(b->runs_dev, b->runs.data(), sizeof(BatchRun) * b->runs.size(),
+                          hipMemcpyHostToDevice, b->stream));
+  GAME_HIP(hipStreamSynchronize(b->stream));
+  b->n_items = (int32_t)items.size();
+  b->tiles_per_item = tiles;
+  if (b->graph) {
+    hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  return GAME_OK;
+}
+
+BatchArgs batch_args(const game_batch_ctx* b) {
+  BatchArgs a{};
+  a.runs = b->runs_dev;
+  a.items = b->items_dev;
+  a.counter = b->counter;
+  a.rank_block_run = b->rank_block_run;
+  a.ga_wave_run = b->ga_wave_run;
+  a.n_runs = b->n_runs;
+  a.n_items = b->n_items;
+  a.n_rank_blocks = b->n_rank_blocks;
+  a.n_ga_waves = b->n_ga_waves;
+  a.max_population = b->max_pop;
+  a.grid = b->grid;
+  return a;
+}
+
+int enqueue_batch_step(game_batch_ctx* b, hipStream_t s) {
+  const BatchArgs a = batch_args(b);
+  GAME_HIP(launch_fitness_batch(a, b->lds, s));
+  GAME_HIP(launch_finish_rank_batch(a, s));
+  GAME_HIP(launch_ga_next_batch(a, s));
+  return GAME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t game_batch_workspace_size(const game_run_desc* runs, int32_t n_runs) {
+  if (!runs || n_runs < 1) {
+    fail(GAME_EINVAL, "no runs");
+    return 0;
+  }
+  for (int i = 0; i < n_runs; ++i)
+    if (check_run(runs[i], i)) return 0;
+  return batch_layout(runs, n_runs).total;
+}
+
+int game_batch_create(const game_run_desc* runs, int32_t n_runs, void* ws, size_t ws_bytes,
+                      void* stream, game_batch_t* out) {
+  if (!out) return fail(GAME_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!runs || n_runs < 1) return fail(GAME_EINVAL, "no runs");
+  for (int i = 0; i < n_runs; ++i) {
+    const int rc = check_run(runs[i], i);
+    if (rc) return rc;
+    if (!runs[i].X_dev || !runs[i].t_dev) return fail(GAME_EINVAL, "run %d: X or t is NULL", i);
+  }
+  if (!ws) return fail(GAME_EWORKSPACE, "workspace is NULL");
+  if (!aligned(ws, kAlign)) return fail(GAME_EWORKSPACE, "workspace not 256-byte aligned");
+  const BatchLayout L = batch_layout(runs, n_runs);
+  if (ws_bytes < L.total)
+    return fail(GAME_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  char* base = (char*)ws;
+  game_batch_ctx* b = new game_batch_ctx{};
+  b->n_runs = n_runs;
+  b->stream = (hipStream_t)stream;
+  b->runs_dev = (BatchRun*)(base + L.runs);
+  b->items_dev = (BatchItem*)(base + L.items);
+  b->counter = (int32_t*)(base + L.counter);
+  b->rank_block_run = (int32_t*)(base + L.rank_map);
+  b->ga_wave_run = (int32_t*)(base + L.ga_map);
+  b->states = (RunState*)(base + L.states);
+  b->item_capacity = L.item_capacity;
+  b->n_rank_blocks = L.n_rank_blocks;
+  b->n_ga_waves = L.n_ga_waves;
+  b->grid = 512;
+  std::vector<int32_t> rank_map, ga_map;
+  size_t lds = 4 * 64 * sizeof(double);
+  for (int i = 0; i < n_runs; ++i) {
+    const game_config& c = runs[i].cfg;
+    b->cfgs.push_back(c);
+    FitArgs fa{};
+    fa.NP = runs[i].n_patterns;
+    fa.N = runs[i].n_features;
+    fa.n_chrom = c.population;
+    plan_fitness(fa, c.degree, c.basis);
+    lds = std::max(lds, fitness_lds_bytes(fa, c.degree));
+    BatchRun r{};
+    r.X = runs[i].X_dev;
+    r.t = runs[i].t_dev;
+    r.NP = runs[i].n_patterns;
+    r.N = runs[i].n_features;
+    r.K = (int32_t)genes_of(&c, r.N);
+    r.basis = c.basis;
+    r.D = c.degree;
+    r.U = fa.U;
+    r.Q = fa.Q;
+    r.pairs_per_chunk = fa.pairs_per_chunk;
+    r.n_chunks = fa.n_chunks;
+    r.n_ctiles = fa.n_ctiles;
+    r.ld_partial = fa.ld_partial;
+    r.n_tiles = fa.n_tiles;
+    r.error_fn = c.error_fn;
+    r.R = c.tmse_R;
+    r.pop0 = (float*)(base + L.pop0[i]);
+    r.pop1 = (float*)(base + L.pop1[i]);
+    r.fit32 = (float*)(base + L.fit32[i]);
+    r.fit64 = (double*)(base + L.fit64[i]);
+    r.order = (int32_t*)(base + L.order[i]);
+    r.partial = (double*)(base + L.partial[i]);
+    r.state = b->states + i;
+    r.P = c.population;
+    r.k = c.tournament_k;
+    r.E = c.elitism;
+    r.elite_mode = c.elite_mode;
+    r.thr_cross = coin_threshold(c.p_crossover);
+    r.thr_mut = coin_threshold(c.p_mutation);
+    r.sigma = c.sigma_mutation;
+    r.seed = c.seed;
+    r.rank_block0 = (int32_t)rank_map.size();
+    for (int k = 0; k < (c.population + kRankPerBlock - 1) / kRankPerBlock; ++k) rank_map.push_back(i);
+    r.ga_wave0 = (int32_t)ga_map.size();
+    for (int k = 0; k < c.elitism + (c.population - c.elitism + 1) / 2; ++k) ga_map.push_back(i);
+    b->runs.push_back(r);
+    b->max_pop = std::max(b->max_pop, c.population);
+    b->max_gen = std::max(b->max_gen, c.max_generations);
+  }
+  b->lds = lds;
+  int rc = GAME_OK;
+  hipError_t e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) rc = hip_fail(e, "hipStreamCreateWithFlags");
+  if (!rc) {
+    e = hipMemcpyAsync(b->rank_block_run, rank_map.data(), sizeof(int32_t) * rank_map.size(),
+                       hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->ga_wave_run, ga_map.data(), sizeof(int32_t) * ga_map.size(),
+                         hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "hipMemcpyAsync");
+  }
+  if (!rc) rc = build_items(b, 8);
+  if (rc) {
+    if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return GAME_OK;
+}
+
+int game_batch_destroy(game_batch_t b) {
+  if (!b) return fail(GAME_EINVAL, "batch is NULL");
+  if (b->graph) hipGraphExecDestroy(b->graph);
+  if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+  delete b;
+  return GAME_OK;
+}
+
+int game_batch_tune(game_batch_t b, int32_t tiles_per_item, int32_t grid) {
+  if (!b) return fail(GAME_EINVAL, "batch is NULL");
+  if (tiles_per_item < 1 || grid < 1 || grid > 65536)
+    return fail(GAME_EINVAL, "tiles_per_item >= 1 and 1 <= grid <= 65536");
+  b->grid = grid;
+  return build_items(b, tiles_per_item);
+}
+
+int game_batch_autotune(game_batch_t b, int32_t reps, int32_t* best_tiles, int32_t* best_grid,
+                        float* best_ms, float* times_ms) {
+  if (!b) return fail(GAME_EINVAL, "batch is NULL");
+  if (reps < 1) return fail(GAME_EINVAL, "reps < 1");
+  static const int kTiles[] = {1, 2, 4, 8, 16, 32};
+  static const int kGrids[] = {256, 512, 1024};
+  hipEvent_t e0, e1;
+  GAME_HIP(hipEventCreate(&e0));
+  GAME_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bt = 8, bg = 512, idx = 0;
+  int rc = GAME_OK;
+  for (int tiles : kTiles) {
+    for (int grid : kGrids) {
+      b->grid = grid;
+      rc = build_items(b, tiles);
+      if (rc) break;
+      const BatchArgs a = batch_args(b);
+      hipError_t e = launch_batch_reset(a, b->stream);
+      if (e == hipSuccess) e = launch_fitness_batch(a, b->lds, b->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+      for (int i = 0; i < reps && e == hipSuccess; ++i) {
+        e = launch_batch_reset(a, b->stream);
+        if (e == hipSuccess) e = launch_fitness_batch(a, b->lds, b->stream);
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        rc = hip_fail(e, "autotune launch");
+        break;
+      }
+      ms /= reps;
+      if (times_ms) times_ms[idx] = ms;
+      ++idx;
+      if (ms < best) {
+        best = ms;
+        bt = tiles;
+        bg = grid;
+      }
+    }
+    if (rc) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  b->grid = bg;
+  rc = build_items(b, bt);
+  if (rc) return rc;
+  GAME_HIP(launch_batch_reset(batch_args(b), b->stream));
+  if (best_tiles) *best_tiles = bt;
+  if (best_grid) *best_grid = bg;
+  if (best_ms) *best_ms = best;
+  return GAME_OK;
+}
+
+int game_batch_init(game_batch_t b) {
+  if (!b) return fail(GAME_EINVAL, "batch is NULL");
+  for (int r = 0; r < b->n_runs; ++r) {
+    const game_config& c = b->cfgs[r];
+    GAME_HIP(launch_init_genes(c.seed, c.init_mode, c.population, b->runs[r].K, b->runs[r].pop0,
+                               b->stream));
+    GAME_HIP(launch_set_state(b->states + r, 0, c.max_generations, c.target, 1, b->stream));
+  }
+  GAME_HIP(launch_batch_reset(batch_args(b), b->stream));
+  b->initialized = true;
+  return GAME_OK;
+}
+
+int game_batch_step(game_batch_t b) {
+  if (!b) return fail(GAME_EINVAL, "batch is NULL");
+  if (!b->initialized) return fail(GAME_ESTATE, "batch not initialised");
+  return enqueue_batch_step(b, b->stream);
+}
+
+int game_batch_run(game_batch_t b, int32_t* gens_done, double* best_err) {
+  if (!b) return fail(GAME_EINVAL, "batch is NULL");
+  if (!b->initialized) return fail(GAME_ESTATE, "batch not initialised");
+  std::vector<RunState> st(b->n_runs);
+  GAME_HIP(hipMemcpyAsync(st.data(), b->states, sizeof(RunState) * b->n_runs,
+                          hipMemcpyDeviceToHost, b->stream));
+  GAME_HIP(hipStreamSynchronize(b->stream));
+  int min_gen = INT32_MAX;
+  for (const RunState& x : st)
+    if (!x.stop) min_gen = std::min(min_gen, x.gen);
+  if (min_gen != INT32_MAX) {
+    if (!b->graph) {
+      const int steps = 4;
+      GAME_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+      int rc = GAME_OK;
+      for (int i = 0; i < steps && rc == GAME_OK; ++i) rc = enqueue_batch_step(b, b->capture_stream);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(b->capture_stream, &g);
+      if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+      }
+      if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+      const hipError_t ei = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        b->graph = nullptr;
+        return hip_fail(ei, "hipGraphInstantiate");
+      }
+      b->graph_steps = steps;
+    }
+    const int64_t evals = (int64_t)b->max_gen - min_gen + 1;
+    const int64_t launches = evals <= 0 ? 1 : (evals + b->graph_steps - 1) / b->graph_steps;
+    for (int64_t i = 0; i < launches; ++i) GAME_HIP(hipGraphLaunch(b->graph, b->stream));
+  }
+  GAME_HIP(hipMemcpyAsync(st.data(), b->states, sizeof(RunState) * b->n_runs,
+                          hipMemcpyDeviceToHost, b->stream));
+  GAME_HIP(hipStreamSynchronize(b->stream));
+  for (int r = 0; r < b->n_runs; ++r) {
+    if (gens_done) gens_done[r] = st[r].gen;
+    if (best_err) best_err[r] = st[r].best_err;
+  }
+  return GAME_OK;
+}
+
+int game_batch_get_population(game_batch_t b, int32_t run, float* genes, float* fitness) {
+  if (!b) return fail(GAME_EINVAL, "batch is NULL");
+  if (run < 0 || run >= b->n_runs) return fail(GAME_EINVAL, "run %d out of range", run);
+  if (!genes) return fail(GAME_EINVAL, "genes is NULL");
+  const BatchRun& r = b->runs[run];
+  const int64_t n = (int64_t)r.P * r.K;
+  hipLaunchKernelGGL(copy_current_kernel,
+                     dim3((unsigned)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024)), dim3(256),
+                     0, b->stream, b->states + run, r.pop0, r.pop1, n, genes);
+  GAME_HIP(hipGetLastError());
+  if (fitness)
+    GAME_HIP(hipMemcpyAsync(fitness, r.fit32, sizeof(float) * r.P, hipMemcpyDeviceToDevice,
+                            b->stream));
+  return GAME_OK;
+}
+
+int game_batch_num_items(game_batch_t b, int32_t* n_items, int32_t* tiles_per_item, int32_t* grid) {
+  if (!b) return fail(GAME_EINVAL, "batch is NULL");
+  if (n_items) *n_items = b->n_items;
+  if (tiles_per_item) *tiles_per_item = b->tiles_per_item;
+  if (grid) *grid = b->grid;
   return GAME_OK;
 }
 

@@ -113,7 +113,7 @@ def binary_problem(name, n, nf, basis, degree, population, generations, seed=0, 
 
 
 def regression_problem(name, n, nf, basis, degree, population, generations, seed=0,
-                       noise=0.05, mixture=0):
+                       noise=0.05, mixture=0, with_validation=True):
     """Regression target teacher(x) + N(0, noise^2); X uniform in [-1, 1] or,
     with ``mixture`` > 0, an equal-weight mixture of that many isotropic
     Gaussians (means U[-0.5, 0.5], widths U[0.2, 0.5]) clipped to [-1, 1]."""
@@ -124,12 +124,14 @@ def regression_problem(name, n, nf, basis, degree, population, generations, seed
         means = rng.uniform(-0.5, 0.5, size=(mixture, nf))
         sigmas = rng.uniform(0.2, 0.5, size=mixture)
     sets = []
-    for s, rows in ((seed, n), (seed + 1, max(1, n // 4))):
+    parts = ((seed, n), (seed + 1, max(1, n // 4))) if with_validation else ((seed, n),)
+    for s, rows in parts:
         r = np.random.default_rng(s) if s != seed else rng
         X = _mixture_x(r, rows, nf, means, sigmas) if mixture else _uniform_x(r, rows, nf)
         y = teacher_values(X, basis, degree, teacher) + noise * r.standard_normal(rows)
         sets.append((X.astype(np.float32), y.astype(np.float32)))
-    (X, t), (Xv, tv) = sets
+    (X, t) = sets[0]
+    (Xv, tv) = sets[1] if with_validation else (X[:0], t[:0])
     return Problem(name, basis, degree, X, t, Xv, tv, teacher, population, generations, False)
 
 
@@ -173,11 +175,12 @@ def batched_shapes(n_runs=256, seed=3):
     return out
 
 
-def batched_problem(shape: RunShape, run_index: int, base_seed=3):
+def batched_problem(shape: RunShape, run_index: int, base_seed=3, with_validation=True):
     """One run of the batched workload: X uniform, teacher + N(0, 0.05^2)."""
     return regression_problem(f"batched{run_index}", shape.n_patterns, shape.n_features,
                               shape.basis, shape.degree, shape.population, 100,
-                              seed=base_seed * 100_003 + run_index)
+                              seed=base_seed * 100_003 + run_index,
+                              with_validation=with_validation)
 
 
 def random_genes(P, K, seed, low=-1.0, high=1.0):

@@ -33,6 +33,18 @@ class game_config(ctypes.Structure):
     ]
 
 
+class game_surrogate_config(ctypes.Structure):
+    _fields_ = [("hidden", c_int32), ("fp32_operands", c_int32), ("archive", c_int32),
+                ("minibatch", c_int32), ("train_steps", c_int32), ("lr", c_float),
+                ("oversample", c_int32), ("audit", c_int32), ("rho_min", c_float),
+                ("min_archive", c_int32), ("seed", c_uint64)]
+
+
+class game_run_desc(ctypes.Structure):
+    _fields_ = [("X_dev", c_void_p), ("t_dev", c_void_p), ("n_patterns", c_int64),
+                ("n_features", c_int32), ("reserved", c_int32), ("cfg", game_config)]
+
+
 class GameError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libgame error {code}: {msg}")
@@ -50,6 +62,8 @@ _SIGS = {
     "game_fitness": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "game_evaluate": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int32,
                                 c_void_p]),
+    "game_rescore64": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int32,
+                                 c_void_p]),
     "game_init_population": (c_int32, [c_void_p]),
     "game_step": (c_int32, [c_void_p]),
     "game_run": (c_int32, [c_void_p, c_int32, c_double, POINTER(c_int32), c_void_p,
@@ -64,6 +78,35 @@ _SIGS = {
                                c_void_p, c_void_p, c_size_t, c_void_p]),
     "game_init_genes": (c_int32, [POINTER(game_config), c_int32, c_void_p, c_void_p]),
     "game_last_error": (ctypes.c_char_p, []),
+    "game_surrogate_config_default": (c_int32, [POINTER(game_surrogate_config)]),
+    "game_surrogate_workspace_size": (c_size_t, [POINTER(game_surrogate_config), c_int32,
+                                                 c_int32]),
+    "game_surrogate_create": (c_int32, [POINTER(game_surrogate_config), c_int32, c_int32,
+                                        c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
+    "game_surrogate_destroy": (c_int32, [c_void_p]),
+    "game_surrogate_num_params": (c_int64, [c_void_p]),
+    "game_surrogate_get_params": (c_int32, [c_void_p, c_void_p]),
+    "game_surrogate_set_params": (c_int32, [c_void_p, c_void_p]),
+    "game_surrogate_predict": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p]),
+    "game_surrogate_gradients": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
+                                           c_void_p]),
+    "game_surrogate_train_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
+    "game_attach_surrogate": (c_int32, [c_void_p, c_void_p]),
+    "game_surrogate_stats": (c_int32, [c_void_p, POINTER(c_float), POINTER(c_int32),
+                                       POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]),
+    "game_batch_workspace_size": (c_size_t, [POINTER(game_run_desc), c_int32]),
+    "game_batch_create": (c_int32, [POINTER(game_run_desc), c_int32, c_void_p, c_size_t, c_void_p,
+                                    POINTER(c_void_p)]),
+    "game_batch_destroy": (c_int32, [c_void_p]),
+    "game_batch_tune": (c_int32, [c_void_p, c_int32, c_int32]),
+    "game_batch_autotune": (c_int32, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32),
+                                      POINTER(c_float), c_void_p]),
+    "game_batch_init": (c_int32, [c_void_p]),
+    "game_batch_step": (c_int32, [c_void_p]),
+    "game_batch_run": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "game_batch_get_population": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "game_batch_num_items": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32),
+                                       POINTER(c_int32)]),
 }
 
 
@@ -163,6 +206,14 @@ def game_evaluate(h, X, t, genes, n, err64) -> None:
     import torch
     _check(lib().game_evaluate(h, _ptr(X, torch.float32), _ptr(t, torch.float32), X.shape[0],
                                _ptr(genes, torch.float32), n, _ptr(err64, torch.float64)))
+
+
+def game_rescore64(h, X, t, genes, n, err64) -> None:
+    """X, t None -> the handle's own data set."""
+    import torch
+    n_patterns = X.shape[0] if X is not None else 0
+    _check(lib().game_rescore64(h, _ptr(X, torch.float32), _ptr(t, torch.float32), n_patterns,
+                                _ptr(genes, torch.float32), n, _ptr(err64, torch.float64)))
 
 
 def game_init_population(h) -> None:
@@ -266,6 +317,12 @@ class Game:
         game_evaluate(self.h, X, t, genes, genes.shape[0], out)
         return out
 
+    def rescore64(self, genes, X=None, t=None):
+        import torch
+        out = torch.empty(genes.shape[0], dtype=torch.float64, device=genes.device)
+        game_rescore64(self.h, X, t, genes, genes.shape[0], out)
+        return out
+
     def init_population(self):
         game_init_population(self.h)
 
@@ -288,3 +345,267 @@ class Game:
 
     def state(self):
         return game_get_state(self.h)
+
+
+# ------------------------------------------------------------------ batches
+AUTOTUNE_TILES = (1, 2, 4, 8, 16, 32)
+AUTOTUNE_GRIDS = (256, 512, 1024)
+
+
+def _descs(problems, cfgs):
+    import torch
+    arr = (game_run_desc * len(problems))()
+    for i, ((X, t), c) in enumerate(zip(problems, cfgs)):
+        arr[i].X_dev = _ptr(X, torch.float32)
+        arr[i].t_dev = _ptr(t, torch.float32)
+        arr[i].n_patterns = X.shape[0]
+        arr[i].n_features = X.shape[1]
+        arr[i].reserved = 0
+        arr[i].cfg = c
+    return arr
+
+
+def game_batch_workspace_size(descs, n_runs) -> int:
+    n = lib().game_batch_workspace_size(descs, n_runs)
+    if n == 0:
+        raise GameError(GAME_EINVAL, game_last_error())
+    return n
+
+
+def game_batch_create(descs, n_runs, workspace, stream=None) -> int:
+    h = c_void_p()
+    _check(lib().game_batch_create(descs, n_runs, _ptr(workspace),
+                                   workspace.numel() * workspace.element_size(), _stream(stream),
+                                   ctypes.byref(h)))
+    return h.value
+
+
+def game_batch_destroy(b) -> None:
+    _check(lib().game_batch_destroy(b))
+
+
+def game_batch_tune(b, tiles_per_item, grid) -> None:
+    _check(lib().game_batch_tune(b, tiles_per_item, grid))
+
+
+def game_batch_autotune(b, reps=3) -> dict:
+    t, g, ms = c_int32(), c_int32(), c_float()
+    times = np.zeros(len(AUTOTUNE_TILES) * len(AUTOTUNE_GRIDS), dtype=np.float32)
+    _check(lib().game_batch_autotune(b, reps, ctypes.byref(t), ctypes.byref(g), ctypes.byref(ms),
+                                     times.ctypes.data_as(c_void_p)))
+    table = {f"{tt}x{gg}": float(times[i * len(AUTOTUNE_GRIDS) + j])
+             for i, tt in enumerate(AUTOTUNE_TILES) for j, gg in enumerate(AUTOTUNE_GRIDS)}
+    return {"tiles_per_item": t.value, "grid": g.value, "ms": ms.value, "times_ms": table}
+
+
+def game_batch_init(b) -> None:
+    _check(lib().game_batch_init(b))
+
+
+def game_batch_step(b) -> None:
+    _check(lib().game_batch_step(b))
+
+
+def game_batch_run(b, n_runs):
+    gens = np.zeros(n_runs, dtype=np.int32)
+    best = np.zeros(n_runs, dtype=np.float64)
+    _check(lib().game_batch_run(b, gens.ctypes.data_as(c_void_p), best.ctypes.data_as(c_void_p)))
+    return gens, best
+
+
+def game_batch_get_population(b, run, genes, fitness=None) -> None:
+    import torch
+    _check(lib().game_batch_get_population(b, run, _ptr(genes, torch.float32),
+                                           _ptr(fitness, torch.float32)))
+
+
+def game_batch_num_items(b):
+    n, t, g = c_int32(), c_int32(), c_int32()
+    _check(lib().game_batch_num_items(b, ctypes.byref(n), ctypes.byref(t), ctypes.byref(g)))
+    return n.value, t.value, g.value
+
+
+class Batch:
+    """Many runs advanced together: problems is a list of (X, t) GPU tensors,
+    cfgs the matching game_config list."""
+
+    def __init__(self, problems, cfgs, stream=None):
+        import torch
+        self.problems = problems
+        self.cfgs = cfgs
+        self.n_runs = len(problems)
+        self.descs = _descs(problems, cfgs)
+        self.n_genes = [game_num_genes(c, X.shape[1]) for (X, _), c in zip(problems, cfgs)]
+        nbytes = game_batch_workspace_size(self.descs, self.n_runs)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=problems[0][0].device)
+        self.h = game_batch_create(self.descs, self.n_runs, self.workspace, stream)
+
+    def close(self):
+        if self.h:
+            game_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tune(self, tiles_per_item, grid):
+        game_batch_tune(self.h, tiles_per_item, grid)
+
+    def autotune(self, reps=3):
+        return game_batch_autotune(self.h, reps)
+
+    def init(self):
+        game_batch_init(self.h)
+
+    def step(self):
+        game_batch_step(self.h)
+
+    def run(self):
+        return game_batch_run(self.h, self.n_runs)
+
+    def population(self, run):
+        import torch
+        dev = self.problems[run][0].device
+        g = torch.empty((self.cfgs[run].population, self.n_genes[run]), dtype=torch.float32,
+                        device=dev)
+        f = torch.empty(self.cfgs[run].population, dtype=torch.float32, device=dev)
+        game_batch_get_population(self.h, run, g, f)
+        return g, f
+
+    def items(self):
+        return game_batch_num_items(self.h)
+
+
+# ---------------------------------------------------------------- surrogate
+def surrogate_config(**kw) -> game_surrogate_config:
+    c = game_surrogate_config()
+    _check(lib().game_surrogate_config_default(ctypes.byref(c)))
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise AttributeError(k)
+        setattr(c, k, v)
+    return c
+
+
+def game_surrogate_config_default() -> game_surrogate_config:
+    return surrogate_config()
+
+
+def game_surrogate_workspace_size(cfg, n_genes, max_batch) -> int:
+    n = lib().game_surrogate_workspace_size(ctypes.byref(cfg), n_genes, max_batch)
+    if n == 0:
+        raise GameError(GAME_EINVAL, game_last_error())
+    return n
+
+
+def game_surrogate_create(cfg, n_genes, max_batch, workspace, stream=None) -> int:
+    h = c_void_p()
+    _check(lib().game_surrogate_create(ctypes.byref(cfg), n_genes, max_batch, _ptr(workspace),
+                                       workspace.numel() * workspace.element_size(),
+                                       _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def game_surrogate_destroy(s) -> None:
+    _check(lib().game_surrogate_destroy(s))
+
+
+def game_surrogate_num_params(s) -> int:
+    return _check(lib().game_surrogate_num_params(s))
+
+
+def game_surrogate_get_params(s, params) -> None:
+    import torch
+    _check(lib().game_surrogate_get_params(s, _ptr(params, torch.float32)))
+
+
+def game_surrogate_set_params(s, params) -> None:
+    import torch
+    _check(lib().game_surrogate_set_params(s, _ptr(params, torch.float32)))
+
+
+def game_surrogate_predict(s, genes, n, y) -> None:
+    import torch
+    _check(lib().game_surrogate_predict(s, _ptr(genes, torch.float32), n, _ptr(y, torch.float32)))
+
+
+def game_surrogate_gradients(s, genes, target, n, grads, y=None) -> None:
+    import torch
+    _check(lib().game_surrogate_gradients(s, _ptr(genes, torch.float32),
+                                          _ptr(target, torch.float32), n,
+                                          _ptr(grads, torch.float32), _ptr(y, torch.float32)))
+
+
+def game_surrogate_train_step(s, genes, target, n) -> None:
+    import torch
+    _check(lib().game_surrogate_train_step(s, _ptr(genes, torch.float32),
+                                           _ptr(target, torch.float32), n))
+
+
+def game_attach_surrogate(h, s) -> None:
+    _check(lib().game_attach_surrogate(h, s))
+
+
+def game_surrogate_stats(s) -> dict:
+    rho, last, total, cnt, steps = c_float(), c_int32(), c_int32(), c_int32(), c_int32()
+    _check(lib().game_surrogate_stats(s, ctypes.byref(rho), ctypes.byref(last),
+                                      ctypes.byref(total), ctypes.byref(cnt), ctypes.byref(steps)))
+    return {"rho": rho.value, "screened_last": last.value, "screened_total": total.value,
+            "archive_count": cnt.value, "adam_steps": steps.value}
+
+
+class Surrogate:
+    """The network plus its torch-allocated workspace."""
+
+    def __init__(self, cfg: game_surrogate_config, n_genes: int, max_batch: int, device="cuda",
+                 stream=None):
+        import torch
+        self.cfg = cfg
+        self.n_genes = n_genes
+        self.max_batch = max_batch
+        nbytes = game_surrogate_workspace_size(cfg, n_genes, max_batch)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.h = game_surrogate_create(cfg, n_genes, max_batch, self.workspace, stream)
+        self.n_params = game_surrogate_num_params(self.h)
+
+    def close(self):
+        if self.h:
+            game_surrogate_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        import torch
+        p = torch.empty(self.n_params, dtype=torch.float32, device=self.workspace.device)
+        game_surrogate_get_params(self.h, p)
+        return p
+
+    def set_params(self, p):
+        game_surrogate_set_params(self.h, p)
+
+    def predict(self, genes):
+        import torch
+        y = torch.empty(genes.shape[0], dtype=torch.float32, device=genes.device)
+        game_surrogate_predict(self.h, genes, genes.shape[0], y)
+        return y
+
+    def gradients(self, genes, target):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=genes.device)
+        y = torch.empty(genes.shape[0], dtype=torch.float32, device=genes.device)
+        game_surrogate_gradients(self.h, genes, target, genes.shape[0], g, y)
+        return g, y
+
+    def train_step(self, genes, target):
+        game_surrogate_train_step(self.h, genes, target, genes.shape[0])
+
+    def stats(self):
+        return game_surrogate_stats(self.h)

@@ -105,3 +105,34 @@ def test_null_arguments_fail_without_gpu():
     rc = L.game_create(ctypes.byref(c), None, None, 10, 7, None, 0, None, ctypes.byref(h))
     assert rc == game.GAME_EINVAL and h.value is None
     assert L.game_config_default(None) == game.GAME_EINVAL
+
+
+def test_run_desc_layout_matches_c(tmp_path):
+    prog = tmp_path / "desc.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "game.h"\n'
+        "int main(void){printf(\"%zu %zu %zu\", sizeof(game_run_desc),"
+        " offsetof(game_run_desc, n_patterns), offsetof(game_run_desc, cfg));return 0;}\n")
+    exe = tmp_path / "desc"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    d = game.game_run_desc
+    assert got == [ctypes.sizeof(d), d.n_patterns.offset, d.cfg.offset]
+
+
+def test_batch_rejects_invalid_runs_without_gpu():
+    descs = (game.game_run_desc * 2)()
+    for i in range(2):
+        descs[i].n_patterns = 1000
+        descs[i].n_features = 5
+        descs[i].cfg = game.config()
+    assert game.lib().game_batch_workspace_size(descs, 2) > 0
+    descs[1].cfg.precision = game.GAME_BF16
+    assert game.lib().game_batch_workspace_size(descs, 2) == 0
+    assert "run 1" in game.game_last_error()
+    descs[1].cfg.precision = game.GAME_FP32
+    descs[1].cfg.degree = 0
+    assert game.lib().game_batch_workspace_size(descs, 2) == 0
+    assert game.lib().game_batch_workspace_size(descs, 0) == 0
