@@ -68,6 +68,15 @@ typedef enum { GAME_FP32 = 0, GAME_BF16 = 1 } game_precision;
  * [-1, 1] (sigma 1/3, clamped), uniform in [-1, 1), uniform in [0, 1). */
 typedef enum { GAME_INIT_NORMAL = 0, GAME_INIT_UNIFORM = 1, GAME_INIT_UNIT = 2 } game_init;
 
+/* Parent selection: a tournament of tournament_k draws with replacement
+ * (lowest (fitness, index) wins), or the two criteria named in Sec. 2:
+ * linear ranking with selection pressure 2 (rank r of P has weight P - r;
+ * integer draw (u32 * P(P+1)/2) >> 32 located in the cumulative weights)
+ * and roulette wheel (weight 1/(error + 1e-12) in float64, cumulative sum
+ * left to right, first index above (u32 2^-32) * total; infinite or NaN
+ * errors weigh 0; a wheel of zero total draws uniformly). */
+typedef enum { GAME_TOURNAMENT = 0, GAME_RANKING = 1, GAME_ROULETTE = 2 } game_selection;
+
 /* Run configuration (the user options of Sec. 2 and the parameters of
  * Sec. 5).  Genetic operators: tournament selection of size tournament_k
  * with replacement (lowest (fitness, index) wins); one-point crossover with
@@ -94,11 +103,13 @@ typedef struct {
   uint64_t seed;
   int32_t max_generations;/* stop after this many evolution steps        */
   double target;          /* stop when the best error <= target (0.001)  */
+  int32_t selection;      /* game_selection                               */
 } game_config;
 
-/* Fills *cfg with the defaults: Chebyshev, d = 4, P = 50, k = 3, elitism 2
- * (mode 0), normal init, MSE, FP32, p_c 0.9, p_m 0.05, sigma 0.1, R 0.49,
- * seed 0, 100 generations, target 0.001.  Returns GAME_EINVAL on NULL. */
+/* Fills *cfg with the defaults: Chebyshev, d = 4, P = 50, tournament of
+ * k = 3, elitism 2 (mode 0), normal init, MSE, FP32, p_c 0.9, p_m 0.05,
+ * sigma 0.1, R 0.49, seed 0, 100 generations, target 0.001.  Returns
+ * GAME_EINVAL on NULL. */
 int game_config_default(game_config* cfg);
 
 /* K = B*N*d + 1 for this configuration and feature count (Eq. 2 with

@@ -10,6 +10,8 @@ tournament of 4, elitism 2, error threshold 0.001), but not the operators'
 exact form nor the random-number scheme.  This module fixes them as follows,
 and the HIP library implements the same reading:
 
+* parents are chosen by tournament (the default), by linear ranking or by
+  roulette wheel (the two criteria named in Sec. 2), defined below;
 * every draw comes from Philox4x64-10 with key (seed, stream) and counter
   (generation, unit, block, 0); stream 0 = initialisation (unit = chromosome,
   block = gene), 1 = selection and crossover (unit = child pair), 2 = mutation
@@ -33,6 +35,7 @@ from .philox import block
 
 STREAM_INIT, STREAM_SELECT, STREAM_MUTATE = 0, 1, 2
 INIT_NORMAL, INIT_UNIFORM, INIT_UNIT = 0, 1, 2
+SELECT_TOURNAMENT, SELECT_RANKING, SELECT_ROULETTE = 0, 1, 2
 
 _M32 = np.uint64(0xFFFFFFFF)
 
@@ -48,6 +51,7 @@ class GAConfig:
     sigma_mutation: float = 0.1
     seed: int = 0
     init_mode: int = INIT_NORMAL
+    selection: int = SELECT_TOURNAMENT
 
 
 def words(blocks_u64: np.ndarray) -> np.ndarray:
@@ -124,14 +128,51 @@ def _tournament(f: np.ndarray, idx: np.ndarray) -> np.ndarray:
     return best
 
 
+def ranking_pick(fit, u32) -> np.ndarray:
+    """Linear ranking with selection pressure 2 (one of the two selection
+    criteria named in Sec. 2): rank r (0 = best) has weight P - r.  The
+    draw t = (u32 * P(P+1)/2) >> 32 picks the rank whose cumulative weight
+    interval contains t."""
+    f = canonical_fitness(fit)
+    P = f.size
+    order = rank_order(f)
+    W = P * (P + 1) // 2
+    t = (np.asarray(u32, dtype=np.uint64) * np.uint64(W)) >> np.uint64(32)
+    r = np.arange(P, dtype=np.int64)
+    cum_end = (r + 1) * P - (r + 1) * r // 2            # weight of ranks 0..r
+    ranks = np.searchsorted(cum_end, t.astype(np.int64), side="right")
+    return order[ranks]
+
+
+def roulette_cumulative(fit) -> np.ndarray:
+    """Roulette wheel (the other criterion of Sec. 2): weight 1/(MSE + 1e-12)
+    in float64 (an infinite or NaN error weighs 0), summed left to right."""
+    f = canonical_fitness(fit).astype(np.float64)
+    w = 1.0 / (f + 1e-12)
+    return np.cumsum(w)
+
+
+def roulette_pick(cum, u32) -> np.ndarray:
+    """First index whose cumulative weight exceeds (u32 2^-32) * total; a
+    wheel of zero total falls back to the uniform index draw."""
+    total = cum[-1]
+    u = np.asarray(u32, dtype=np.uint64)
+    if not total > 0:
+        return index_draw(u, cum.size).astype(np.int64)
+    target = (u.astype(np.float64) * 2.0 ** -32) * total
+    return np.minimum(np.searchsorted(cum, target, side="right"), cum.size - 1).astype(np.int64)
+
+
 def select_pairs(fit, P: int, K: int, generation: int, cfg: GAConfig):
-    """Tournament selection and crossover decisions for every child pair.
+    """Parent selection and crossover decisions for every child pair.
 
     Returns (parent1, parent2, crossover, cut), each of length
-    ceil((P - E) / 2).  Pair q reads stream-1 words in order: k indices for
-    parent 1, k for parent 2, the crossover coin, then the cut point
+    ceil((P - E) / 2).  Pair q reads stream-1 words in order: the draws for
+    parent 1 and parent 2 (k words each for a tournament of size k, one word
+    each for ranking and roulette), the crossover coin, then the cut point
     1 + (u32 * (K - 1)) >> 32, a cut in [1, K-1]."""
-    E, k = cfg.elitism, cfg.tournament_k
+    E = cfg.elitism
+    k = cfg.tournament_k if cfg.selection == SELECT_TOURNAMENT else 1
     n_pairs = (P - E + 1) // 2
     f = canonical_fitness(fit)
     n_words = 2 * k + 2
@@ -139,8 +180,18 @@ def select_pairs(fit, P: int, K: int, generation: int, cfg: GAConfig):
     q = np.arange(n_pairs, dtype=np.uint64)[:, None]
     bl = np.arange(n_blocks, dtype=np.uint64)[None, :]
     w = words(block(cfg.seed, STREAM_SELECT, generation, q, bl)).reshape(n_pairs, -1)
-    p1 = _tournament(f, index_draw(w[:, 0:k], P).astype(np.int64))
-    p2 = _tournament(f, index_draw(w[:, k:2 * k], P).astype(np.int64))
+    if cfg.selection == SELECT_TOURNAMENT:
+        p1 = _tournament(f, index_draw(w[:, 0:k], P).astype(np.int64))
+        p2 = _tournament(f, index_draw(w[:, k:2 * k], P).astype(np.int64))
+    elif cfg.selection == SELECT_RANKING:
+        p1 = ranking_pick(f, w[:, 0])
+        p2 = ranking_pick(f, w[:, 1])
+    elif cfg.selection == SELECT_ROULETTE:
+        cum = roulette_cumulative(f)
+        p1 = roulette_pick(cum, w[:, 0])
+        p2 = roulette_pick(cum, w[:, 1])
+    else:
+        raise ValueError(f"unknown selection {cfg.selection}")
     cross = w[:, 2 * k] < np.uint64(coin_threshold(cfg.p_crossover))
     cut = (1 + index_draw(w[:, 2 * k + 1], K - 1)).astype(np.int64)
     return p1, p2, cross, cut

@@ -117,7 +117,12 @@ struct GAArgs {
   uint64_t seed;
   int32_t n_slots;          // output slots incl. elites; 0 means P
   float* children;          // when set, child slot s goes to row s - E here
+  int32_t selection;        // 0 tournament, 1 linear ranking, 2 roulette
+  const double* cum;        // roulette: cumulative weights [P]
 };
+// Roulette wheel of one generation: cum[i] = sum_{j<=i} 1/(f_j + 1e-12).
+hipError_t launch_roulette_cum(const float* fit, int32_t P, double* cum, const int32_t* stop,
+                               hipStream_t s);
 hipError_t launch_ga_next(const GAArgs& a, hipStream_t s);
 
 // Evaluation epilogue of a run: float64 errors, rank, best, stop test.
@@ -177,6 +182,8 @@ struct BatchRun {
   uint64_t thr_mut;
   float sigma;
   uint64_t seed;
+  int32_t selection;
+  double* cum;              // roulette weights [P]
   int32_t rank_block0;      // first rank workgroup of this run
   int32_t ga_wave0;         // first genetic-step wave of this run
 };
@@ -207,6 +214,7 @@ hipError_t launch_fitness_batch(const BatchArgs& a, size_t lds_bytes, hipStream_
 hipError_t launch_finish_rank_batch(const BatchArgs& a, hipStream_t s);
 hipError_t launch_ga_next_batch(const BatchArgs& a, hipStream_t s);
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
+hipError_t launch_roulette_cum_batch(const BatchArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- surrogate
 struct GemmArgs {

@@ -3,8 +3,10 @@
 // Same contraction as the float32 kernel (Eq. 2 over NP patterns, then the
 // error of Eqs. 3-5/10), with the expansion values and the genes rounded to
 // bfloat16 (round to nearest even) and fed to v_mfma_f32_32x32x16_bf16;
-// products accumulate in float32.  The bias gene stays float32 and is added
-// to the accumulated sum in the epilogue.  Squared
+// products accumulate in float32.  The bias gene and the target stay exact:
+// one extra K-step multiplies the three-part bfloat16 splits of a_0 and of
+// -t_k (hi + mid + lo reproduces a float32 exactly) by ones, so the
+// accumulator ends at Out - t and the epilogue only squares and sums.  Squared
 // residuals are summed in float32 per tile and the tile sums are added with
 // Neumaier compensation, so the reduction over a million patterns adds no
 // error beyond the per-tile float32 sums.
@@ -44,6 +46,18 @@ constexpr int group_size(int d) {
   return g0 * r;
 }
 
+// x = p[0] + p[1] + p[2] exactly (three bfloat16 parts, round to nearest
+// even, each taking the next 8 significant bits of the remainder).
+__device__ __forceinline__ void split3(float x, bf16x8& p) {
+  const __bf16 hi = (__bf16)x;
+  const float r1 = x - (float)hi;
+  const __bf16 mid = (__bf16)r1;
+  const __bf16 lo = (__bf16)(r1 - (float)mid);
+  p[0] = hi;
+  p[1] = mid;
+  p[2] = lo;
+}
+
 // LDS row stride for one chromosome: 32 bytes per K-step (two lane halves x
 // 8 bf16) plus 16 bytes so that rows start 4 banks apart.
 __host__ __device__ constexpr int bf16_row_bytes(int ksteps) { return ksteps * 32 + 16; }
@@ -79,11 +93,22 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
   const int RS = bf16_row_bytes(ks_chunk); // LDS row stride in bytes
   const int K = a.K;
 
-  float w0[4];
+  // B fragments of the bias K-step: lane half 0 carries the split bias of
+  // its chromosome, half 1 ones (they multiply the split targets).
+  bf16x8 bbias[4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
     const int n = c0 + cb * 32 + m;
-    w0[cb] = n < a.n_chrom ? genes[(int64_t)n * K] : 0.f;
+    const float w0 = n < a.n_chrom ? genes[(int64_t)n * K] : 0.f;
+    bf16x8 v = {};
+    if (h == 0) {
+      split3(w0, v);
+    } else {
+      v[0] = (__bf16)1.f;
+      v[1] = (__bf16)1.f;
+      v[2] = (__bf16)1.f;
+    }
+    bbias[cb] = v;
   }
 
   // Stage groups [chunk*gpc, chunk*gpc + gpc): value p (0..G*D-1) of lane
@@ -160,14 +185,22 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
 
   for (int tile = tile_begin; tile < tile_end; ++tile) {
     const int64_t row0 = (int64_t)tile * kTileRows + wave * 64;
-    const float t_lane = a.t[row0 + lane < NP ? row0 + lane : NP - 1];
-    // Accumulators start at zero (an inline constant, nothing to keep live
-    // across tiles); the bias joins in the epilogue.
+    // Bias K-step: accumulators start at a_0 - t_k, exactly.
     f32x16 acc[2][4];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      acc[0][cb] = f32x16{};
-      acc[1][cb] = f32x16{};
+    for (int rb = 0; rb < 2; ++rb) {
+      bf16x8 abias = {};
+      if (h == 0) {
+        abias[0] = (__bf16)1.f;
+        abias[1] = (__bf16)1.f;
+        abias[2] = (__bf16)1.f;
+      } else {
+        const int64_t r = row0 + rb * 32 + m;
+        split3(-a.t[r < NP ? r : NP - 1], abias);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(abias, bbias[cb], f32x16{}, 0, 0, 0);
     }
 
     for (int chunk = 0; chunk < a.n_chunks; ++chunk) {
@@ -231,26 +264,34 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
       }
     }
 
-    // Epilogue, one code path for every error function: with the
-    // convergence tube (TMSE) the squared residual counts when its key
-    // exceeds R (key |r|, or r^2 for the printed form of Eq. 10); MSE and
-    // RMSE keep every term, so a NaN residual propagates to the sum.
+    // Epilogue: the accumulators hold Out - t.  MSE/RMSE sum the squares
+    // (a NaN propagates); the convergence tube keeps a square when its key
+    // exceeds R (|r| for TMSE, r^2 for the printed form of Eq. 10).  Rows
+    // past the data count only in the ragged last tile.
     const bool full = row0 + 64 <= NP;
     float s[4] = {0.f, 0.f, 0.f, 0.f};
+    if (!tube && full) {
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
+      for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int rl = rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-        const float tv = __shfl(t_lane, rl);
-        const bool ok = full || (row0 + rl < NP);
+        for (int i = 0; i < 16; ++i)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          const float v = (acc[rb][cb][i] + w0[cb]) - tv;
-          const float e = v * v;
-          const float key = key_sq ? e : fabsf(v);
-          const float kept = tube ? (key > thr ? e : 0.f) : e;
-          s[cb] += ok ? kept : 0.f;
+          for (int cb = 0; cb < 4; ++cb) s[cb] = fmaf(acc[rb][cb][i], acc[rb][cb][i], s[cb]);
+    } else {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int rl = rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+          const bool ok = full || (row0 + rl < NP);
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) {
+            const float v = acc[rb][cb][i];
+            const float e = v * v;
+            const float key = key_sq ? e : fabsf(v);
+            const float kept = tube ? (key > thr ? e : 0.f) : e;
+            s[cb] += ok ? kept : 0.f;
+          }
         }
       }
     }

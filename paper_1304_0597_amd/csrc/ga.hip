@@ -268,6 +268,69 @@ __device__ __forceinline__ int tournament(const float* fit, const uint32_t* w, i
 
 constexpr int kMaxTournament = 64;
 
+// Linear ranking, pressure 2: rank r has weight P - r; the integer draw
+// t = (u32 * P(P+1)/2) >> 32 falls in rank r's cumulative interval.
+__device__ __forceinline__ int ranking_pick(const int32_t* order, int P, uint32_t u) {
+  const int64_t W = (int64_t)P * (P + 1) / 2;
+  const int64_t t = (int64_t)(((uint64_t)u * (uint64_t)W) >> 32);
+  int lo = 0, hi = P - 1;                 // first r with cum_end(r) > t
+  while (lo < hi) {
+    const int r = (lo + hi) >> 1;
+    const int64_t cum_end = (int64_t)(r + 1) * P - (int64_t)(r + 1) * r / 2;
+    if (cum_end > t) hi = r;
+    else lo = r + 1;
+  }
+  return order[lo];
+}
+
+// Roulette wheel: first index whose cumulative weight exceeds
+// (u32 2^-32) * total; zero total draws uniformly.
+__device__ __forceinline__ int roulette_pick(const double* cum, int P, uint32_t u) {
+  const double total = cum[P - 1];
+  if (!(total > 0.0)) return (int)(((uint64_t)u * (uint64_t)P) >> 32);
+  const double target = ((double)u * 0x1p-32) * total;
+  int lo = 0, hi = P;                      // first i with cum[i] > target
+  while (lo < hi) {
+    const int i = (lo + hi) >> 1;
+    if (cum[i] > target) hi = i;
+    else lo = i + 1;
+  }
+  return lo < P ? lo : P - 1;
+}
+
+// Roulette weights in parallel, then one fixed left-to-right float64 scan.
+__device__ void roulette_cum_body(const float* fit, int P, double* cum, double* w) {
+  for (int i = threadIdx.x; i < P; i += blockDim.x)
+    w[i] = 1.0 / ((double)rank_key_value(fit[i]) + 1e-12);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < P; ++i) {
+      s += w[i];
+      cum[i] = s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void roulette_cum_kernel(const float* fit, int P, double* cum,
+                                                            const int32_t* stop) {
+  extern __shared__ double w[];
+  if (stop && *stop) return;
+  roulette_cum_body(fit, P, cum, w);
+}
+
+hipError_t launch_roulette_cum(const float* fit, int32_t P, double* cum, const int32_t* stop,
+                               hipStream_t s) {
+  const size_t lds = (size_t)P * sizeof(double);
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)roulette_cum_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(roulette_cum_kernel, dim3(1), dim3(1024), lds, s, fit, P, cum, stop);
+  return hipGetLastError();
+}
+
 // Body of one wave: output group `wid` (an elite slot, or child pair
 // wid - E) of the run described by `a`.
 __device__ void ga_next_wave(const GAArgs& a, int wid) {
@@ -298,7 +361,8 @@ __device__ void ga_next_wave(const GAArgs& a, int wid) {
 
   // selection words for pair q
   uint32_t w[2 * kMaxTournament + 2];
-  const int n_words = 2 * a.k + 2;
+  const int k = a.selection == 0 ? a.k : 1;
+  const int n_words = 2 * k + 2;
   for (int b = 0; b * 8 < n_words; ++b) {
     const U64x4 r = draw(a.seed, 1, (uint64_t)gen, (uint64_t)q, (uint64_t)b);
     const uint64_t o[4] = {r.o0, r.o1, r.o2, r.o3};
@@ -308,10 +372,19 @@ __device__ void ga_next_wave(const GAArgs& a, int wid) {
       if (idx < n_words) w[idx] = (i & 1) ? (uint32_t)(o[i >> 1] >> 32) : (uint32_t)o[i >> 1];
     }
   }
-  const int p1 = tournament(a.fitness, w, a.k, P);
-  const int p2 = tournament(a.fitness, w + a.k, a.k, P);
-  const bool cross = (uint64_t)w[2 * a.k] < a.thr_cross;
-  const int cut = 1 + (int)(((uint64_t)w[2 * a.k + 1] * (uint64_t)(K - 1)) >> 32);
+  int p1, p2;
+  if (a.selection == 1) {
+    p1 = ranking_pick(a.order, P, w[0]);
+    p2 = ranking_pick(a.order, P, w[1]);
+  } else if (a.selection == 2) {
+    p1 = roulette_pick(a.cum, P, w[0]);
+    p2 = roulette_pick(a.cum, P, w[1]);
+  } else {
+    p1 = tournament(a.fitness, w, k, P);
+    p2 = tournament(a.fitness, w + k, k, P);
+  }
+  const bool cross = (uint64_t)w[2 * k] < a.thr_cross;
+  const int cut = 1 + (int)(((uint64_t)w[2 * k + 1] * (uint64_t)(K - 1)) >> 32);
 
   const int sa = E + 2 * q, sb = sa + 1;
   const bool has_b = sb < n_slots;
@@ -410,12 +483,34 @@ __global__ __launch_bounds__(256) void ga_next_batch_kernel(BatchArgs a) {
   g.thr_mut = run.thr_mut;
   g.sigma = run.sigma;
   g.seed = run.seed;
+  g.selection = run.selection;
+  g.cum = run.cum;
   ga_next_wave(g, gw - run.ga_wave0);
 }
 
 hipError_t launch_ga_next_batch(const BatchArgs& a, hipStream_t s) {
   const int blocks = (a.n_ga_waves + 3) / 4;
   hipLaunchKernelGGL(ga_next_batch_kernel, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// Roulette wheels of every run that selects by roulette: workgroup r
+// serves run r.
+__global__ __launch_bounds__(1024) void roulette_cum_batch_kernel(BatchArgs a) {
+  extern __shared__ double w[];
+  const BatchRun& run = a.runs[blockIdx.x];
+  if (run.selection != 2 || run.state->stop) return;
+  roulette_cum_body(run.fit32, run.P, run.cum, w);
+}
+
+hipError_t launch_roulette_cum_batch(const BatchArgs& a, hipStream_t s) {
+  const size_t lds = (size_t)a.max_population * sizeof(double);
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)roulette_cum_batch_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(roulette_cum_batch_kernel, dim3(a.n_runs), dim3(1024), lds, s, a);
   return hipGetLastError();
 }
 

@@ -79,6 +79,8 @@ int check_config(const game_config* c, int32_t n_features) {
       !(c->tmse_R > 0.f && c->tmse_R < 1.f))
     return fail(GAME_EINVAL, "tmse_R must lie in (0, 1)");
   if (c->max_generations < 0) return fail(GAME_EINVAL, "max_generations < 0");
+  if (c->selection < 0 || c->selection > 2)
+    return fail(GAME_EINVAL, "selection %d not in 0..2", c->selection);
   if (n_features < 1) return fail(GAME_EINVAL, "n_features %d < 1", n_features);
   if (genes_of(c, n_features) > kMaxGenes)
     return fail(GAME_EINVAL, "B*N*d+1 = %lld genes exceeds %d", (long long)genes_of(c, n_features),
@@ -87,7 +89,7 @@ int check_config(const game_config* c, int32_t n_features) {
 }
 
 struct Layout {
-  size_t state, pop0, pop1, fit32, fit64, order, partial, rescore, total;
+  size_t state, pop0, pop1, fit32, fit64, order, cum, partial, rescore, total;
 };
 
 Layout layout(const game_config* c, int32_t n_features) {
@@ -102,6 +104,7 @@ Layout layout(const game_config* c, int32_t n_features) {
   L.fit32 = off; off += align_up(P * sizeof(float));
   L.fit64 = off; off += align_up(P * sizeof(double));
   L.order = off; off += align_up(P * sizeof(int32_t));
+  L.cum = off; off += align_up(P * sizeof(double));
   L.partial = off; off += align_up(Ppad * kMaxSplits * sizeof(double));
   L.rescore = off; off += align_up(64 * sizeof(double));
   L.total = off;
@@ -126,6 +129,7 @@ struct game_ctx {
   float* fit32;
   double* fit64;
   int32_t* order;
+  double* cum;              // roulette wheel of the current generation
   double* partial;
   double* rescore;          // float64 error of the last re-scored elite
   bool initialized;
@@ -217,6 +221,7 @@ GAArgs ga_args(const game_config* c, int32_t K) {
   g.thr_mut = coin_threshold(c->p_mutation);
   g.sigma = c->sigma_mutation;
   g.seed = c->seed;
+  g.selection = c->selection;
   return g;
 }
 
@@ -390,6 +395,7 @@ int enqueue_screening(game_ctx* h, hipStream_t s) {
   ga.stop = stop;
   ga.n_slots = E + C;
   ga.children = sr->cand;
+  ga.cum = h->cum;
   GAME_HIP(launch_ga_next(ga, s));
   int rc = sur_forward(sr, sr->cand, C, nullptr, sr->H1c, nullptr, sr->H2c, sr->yc, stop, s);
   if (rc) return rc;
@@ -429,8 +435,11 @@ int enqueue_step(game_ctx* h, hipStream_t s) {
   ra.order = h->order;
   ra.state = h->state;
   GAME_HIP(launch_finish_rank(ra, s));
+  if (h->cfg.selection == GAME_ROULETTE)
+    GAME_HIP(launch_roulette_cum(h->fit32, h->cfg.population, h->cum, &h->state->stop, s));
   if (h->sur) return enqueue_screening(h, s);
   GAArgs ga = ga_args(&h->cfg, h->K);
+  ga.cum = h->cum;
   ga.pop_a = h->pop[0];
   ga.pop_b = h->pop[1];
   ga.out_a = h->pop[0];
@@ -523,6 +532,7 @@ int game_create(const game_config* c, const float* X, const float* t, int64_t NP
   h->fit64 = (double*)(base + L.fit64);
   h->order = (int32_t*)(base + L.order);
   h->partial = (double*)(base + L.partial);
+  h->cum = (double*)(base + L.cum);
   h->rescore = (double*)(base + L.rescore);
   hipError_t e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
@@ -723,7 +733,8 @@ size_t game_ga_workspace_size(const game_config* c) {
     fail(GAME_EINVAL, "population %d not in 2..%d", c->population, kMaxPopulation);
     return 0;
   }
-  return align_up((size_t)c->population * sizeof(int32_t));
+  return align_up((size_t)c->population * sizeof(int32_t)) +
+         align_up((size_t)c->population * sizeof(double));
 }
 
 int game_ga_next(const game_config* c, int32_t K, const float* pop, const float* fitness,
@@ -741,8 +752,12 @@ int game_ga_next(const game_config* c, int32_t K, const float* pop, const float*
     return fail(GAME_EINVAL, "out overlaps pop");
   hipStream_t s = (hipStream_t)stream;
   int32_t* order = (int32_t*)ws;
+  double* cum = (double*)((char*)ws + align_up((size_t)c->population * sizeof(int32_t)));
   GAME_HIP(launch_rank(fitness, c->population, order, s));
+  if (c->selection == GAME_ROULETTE)
+    GAME_HIP(launch_roulette_cum(fitness, c->population, cum, nullptr, s));
   GAArgs ga = ga_args(c, K);
+  ga.cum = cum;
   ga.pop_a = pop;
   ga.out_a = out;
   ga.fitness = fitness;
@@ -966,13 +981,14 @@ struct game_batch_ctx {
   hipGraphExec_t graph;
   int graph_steps;
   bool initialized;
+  bool any_roulette;
 };
 
 namespace {
 
 struct BatchLayout {
   size_t runs, items, counter, rank_map, ga_map, states, total;
-  std::vector<size_t> pop0, pop1, fit32, fit64, order, partial;
+  std::vector<size_t> pop0, pop1, fit32, fit64, order, cum, partial;
   int64_t item_capacity;
   int32_t n_rank_blocks, n_ga_waves;
 };
@@ -1019,6 +1035,7 @@ BatchLayout batch_layout(const game_run_desc* runs, int32_t n) {
     L.fit32.push_back(off); off += align_up(P * sizeof(float));
     L.fit64.push_back(off); off += align_up(P * sizeof(double));
     L.order.push_back(off); off += align_up(P * sizeof(int32_t));
+    L.cum.push_back(off); off += align_up(P * sizeof(double));
     L.partial.push_back(off); off += align_up(Ppad * kMaxSplits * sizeof(double));
   }
   L.total = off;
@@ -1080,6 +1097,7 @@ int enqueue_batch_step(game_batch_ctx* b, hipStream_t s) {
   const BatchArgs a = batch_args(b);
   GAME_HIP(launch_fitness_batch(a, b->lds, s));
   GAME_HIP(launch_finish_rank_batch(a, s));
+  if (b->any_roulette) GAME_HIP(launch_roulette_cum_batch(a, s));
   GAME_HIP(launch_ga_next_batch(a, s));
   return GAME_OK;
 }
@@ -1170,12 +1188,15 @@ int game_batch_create(const game_run_desc* runs, int32_t n_runs, void* ws, size_
     r.thr_mut = coin_threshold(c.p_mutation);
     r.sigma = c.sigma_mutation;
     r.seed = c.seed;
+    r.selection = c.selection;
+    r.cum = (double*)(base + L.cum[i]);
     r.rank_block0 = (int32_t)rank_map.size();
     for (int k = 0; k < (c.population + kRankPerBlock - 1) / kRankPerBlock; ++k) rank_map.push_back(i);
     r.ga_wave0 = (int32_t)ga_map.size();
     for (int k = 0; k < c.elitism + (c.population - c.elitism + 1) / 2; ++k) ga_map.push_back(i);
     b->runs.push_back(r);
     b->max_pop = std::max(b->max_pop, c.population);
+    if (c.selection == GAME_ROULETTE) b->any_roulette = true;
     b->max_gen = std::max(b->max_gen, c.max_generations);
   }
   b->lds = lds;

@@ -20,6 +20,7 @@ GAME_CHEBYSHEV, GAME_LEGENDRE, GAME_POWER, GAME_TRIG = 0, 1, 2, 3
 GAME_MSE, GAME_RMSE, GAME_TMSE, GAME_TMSE_SQUARED = 0, 1, 2, 3
 GAME_FP32, GAME_BF16 = 0, 1
 GAME_INIT_NORMAL, GAME_INIT_UNIFORM, GAME_INIT_UNIT = 0, 1, 2
+GAME_TOURNAMENT, GAME_RANKING, GAME_ROULETTE = 0, 1, 2
 
 
 class game_config(ctypes.Structure):
@@ -29,7 +30,7 @@ class game_config(ctypes.Structure):
         ("init_mode", c_int32), ("error_fn", c_int32), ("precision", c_int32),
         ("p_crossover", c_float), ("p_mutation", c_float), ("sigma_mutation", c_float),
         ("tmse_R", c_float), ("seed", c_uint64), ("max_generations", c_int32),
-        ("target", c_double),
+        ("target", c_double), ("selection", c_int32),
     ]
 
 

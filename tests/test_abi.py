@@ -38,9 +38,10 @@ def test_config_struct_layout_matches_c(tmp_path):
     prog = tmp_path / "layout.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "game.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu\", sizeof(game_config),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\", sizeof(game_config),"
         " offsetof(game_config, p_crossover), offsetof(game_config, seed),"
-        " offsetof(game_config, max_generations), offsetof(game_config, target));return 0;}\n")
+        " offsetof(game_config, max_generations), offsetof(game_config, target),"
+        " offsetof(game_config, selection));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
                    check=True)
@@ -48,7 +49,7 @@ def test_config_struct_layout_matches_c(tmp_path):
                                           check=True).stdout.split()]
     g = game.game_config
     assert got == [ctypes.sizeof(g), g.p_crossover.offset, g.seed.offset,
-                   g.max_generations.offset, g.target.offset]
+                   g.max_generations.offset, g.target.offset, g.selection.offset]
 
 
 def test_defaults_and_gene_counts():
@@ -64,7 +65,7 @@ def test_defaults_and_gene_counts():
     ("basis", 4), ("degree", 0), ("degree", 17), ("population", 1), ("population", 8193),
     ("tournament_k", 0), ("tournament_k", 65), ("elitism", 50), ("elite_mode", 2),
     ("init_mode", 3), ("error_fn", 4), ("p_crossover", 1.5), ("p_mutation", -0.1),
-    ("sigma_mutation", -1.0), ("max_generations", -1),
+    ("sigma_mutation", -1.0), ("max_generations", -1), ("selection", 3), ("selection", -1),
 ])
 def test_invalid_configs_are_rejected(field, value):
     c = game.config()

@@ -41,7 +41,7 @@ def make_runs(gg, runs=RUNS, max_gen=6, seed0=11):
         cfgs.append(gg.config(basis=basis, degree=d, population=P, seed=100 + i,
                               tournament_k=3, elitism=2, elite_mode=i % 2,
                               p_mutation=0.05 + 0.05 * (i % 3), max_generations=max_gen,
-                              target=0.0))
+                              target=0.0, selection=i % 3))
         host.append((X, t))
     return problems, cfgs, host
 
@@ -50,7 +50,7 @@ def oracle_cfg(c):
     return oga.GAConfig(population=c.population, tournament_k=c.tournament_k, elitism=c.elitism,
                         elite_mode=c.elite_mode, p_crossover=c.p_crossover,
                         p_mutation=c.p_mutation, sigma_mutation=c.sigma_mutation, seed=c.seed,
-                        init_mode=c.init_mode)
+                        init_mode=c.init_mode, selection=c.selection)
 
 
 def test_batch_generations_follow_oracle(gg):

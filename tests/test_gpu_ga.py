@@ -28,7 +28,7 @@ def oracle_cfg(c):
     return oga.GAConfig(population=c.population, tournament_k=c.tournament_k, elitism=c.elitism,
                         elite_mode=c.elite_mode, p_crossover=c.p_crossover,
                         p_mutation=c.p_mutation, sigma_mutation=c.sigma_mutation, seed=c.seed,
-                        init_mode=c.init_mode)
+                        init_mode=c.init_mode, selection=c.selection)
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2])
@@ -187,3 +187,61 @@ def test_resume_is_bit_exact(gg):
     assert np.array_equal(bits(pop_res.cpu().numpy()), bits(pop_full.cpu().numpy()))
     for g in (g1, g2, g3):
         g.close()
+
+
+SELECTION_CASES = [
+    # P, K, E, mode, pc, pm, sigma
+    (50, 29, 2, 0, 0.9, 0.05, 0.1),
+    (2048, 161, 2, 1, 0.9, 0.05, 0.1),
+    (4096, 257, 2, 0, 0.9, 0.2, 0.1),
+    (33, 5, 0, 0, 1.0, 1.0, 2.0),
+    (7, 11, 3, 1, 0.5, 0.5, 0.7),
+]
+
+
+@pytest.mark.parametrize("selection", [1, 2])
+@pytest.mark.parametrize("case", SELECTION_CASES, ids=lambda c: "-".join(map(str, c)))
+def test_ranking_and_roulette_bit_exact(gg, selection, case):
+    P, K, E, mode, pc, pm, sigma = case
+    rng = np.random.default_rng(P + K + selection)
+    pop = rng.uniform(-1, 1, (P, K)).astype(np.float32)
+    fit = rng.uniform(0, 1, P).astype(np.float32) ** 3
+    fit[rng.choice(P, max(1, P // 10), replace=False)] = fit[0]          # ties
+    fit[rng.choice(P, max(1, P // 20), replace=False)] = np.inf
+    fit[rng.choice(P, max(1, P // 20), replace=False)] = np.nan
+    c = gg.config(population=P, elitism=E, elite_mode=mode, p_crossover=pc, p_mutation=pm,
+                  sigma_mutation=sigma, seed=99, selection=selection)
+    ws = torch.empty(gg.game_ga_workspace_size(c), dtype=torch.uint8, device="cuda")
+    out = torch.empty((P, K), dtype=torch.float32, device="cuda")
+    gg.game_ga_next(c, K, torch.from_numpy(pop).cuda(), torch.from_numpy(fit).cuda(), 3, out, ws)
+    torch.cuda.synchronize()
+    ref = oga.ga_next(pop, fit, 3, oracle_cfg(c))
+    assert np.array_equal(bits(out.cpu().numpy()), bits(ref))
+
+
+def test_roulette_all_infinite_is_uniform_and_exact(gg):
+    P, K = 40, 9
+    pop = np.random.default_rng(1).uniform(-1, 1, (P, K)).astype(np.float32)
+    fit = np.full(P, np.inf, np.float32)
+    c = gg.config(population=P, elitism=1, seed=5, selection=2)
+    ws = torch.empty(gg.game_ga_workspace_size(c), dtype=torch.uint8, device="cuda")
+    out = torch.empty((P, K), dtype=torch.float32, device="cuda")
+    gg.game_ga_next(c, K, torch.from_numpy(pop).cuda(), torch.from_numpy(fit).cuda(), 1, out, ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(bits(out.cpu().numpy()), bits(oga.ga_next(pop, fit, 1, oracle_cfg(c))))
+
+
+@pytest.mark.parametrize("selection", [1, 2])
+def test_selection_modes_in_the_loop(gg, selection):
+    prob, c, g = _small_game(gg, selection=selection)
+    g.init_population()
+    ocfg = oracle_cfg(c)
+    for gen in range(6):
+        pop_g, _ = g.population()
+        g.step()
+        _, fit_g = g.population()
+        pop_next, _ = g.population()
+        pop_g, fit_g, pop_next = (x.cpu().numpy() for x in (pop_g, fit_g, pop_next))
+        ref_next = oga.ga_next(pop_g, fit_g, gen + 1, ocfg)
+        assert np.array_equal(bits(pop_next), bits(ref_next)), gen
+    g.close()

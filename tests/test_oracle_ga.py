@@ -210,3 +210,58 @@ def test_run_best_fitness_non_increasing_and_stop_rules():
     res0 = ga.run(X, t, prob.basis, prob.degree, cfg, max_generations=15, target=1e9)
     assert res0["generations"] == 0
     assert np.all(np.abs(res["population"]) <= 1)
+
+
+# ------------------------------------------------------- ranking / roulette
+def test_ranking_probabilities_are_linear():
+    """Rank r of P is drawn with probability (P - r) / (P (P + 1) / 2)."""
+    P = 8
+    fit = np.random.default_rng(0).permutation(P).astype(np.float32)   # rank of i = fit[i]
+    u = ga.words(block(1, 1, 1, np.arange(40000, dtype=np.uint64), 0)).ravel()
+    picks = ga.ranking_pick(fit, u)
+    ranks = fit[picks].astype(np.int64)
+    counts = np.bincount(ranks, minlength=P)
+    expected = (P - np.arange(P)) / (P * (P + 1) / 2) * u.size
+    assert stats.chisquare(counts, expected).pvalue > 1e-4
+
+
+def test_ranking_exact_boundaries():
+    """The integer cumulative weights put draw t = 0 on rank 0 and the
+    largest draw on rank P - 1."""
+    fit = np.array([0.3, 0.1, 0.2], np.float32)       # order: 1, 2, 0
+    assert ga.ranking_pick(fit, np.array([0], np.uint64))[0] == 1
+    assert ga.ranking_pick(fit, np.array([2 ** 32 - 1], np.uint64))[0] == 0
+    # W = 6: ranks own [0,3), [3,5), [5,6); t = (u * 6) >> 32
+    u_for = lambda t: np.array([int(np.ceil(t * 2 ** 32 / 6))], np.uint64)
+    assert ga.ranking_pick(fit, u_for(3))[0] == 2 and ga.ranking_pick(fit, u_for(5))[0] == 0
+
+
+def test_roulette_probabilities_follow_inverse_error():
+    fit = np.array([1.0, 0.5, 0.25, np.inf, np.nan], np.float32)
+    cum = ga.roulette_cumulative(fit)
+    assert cum[-1] == cum[2]                           # inf and NaN weigh 0
+    u = ga.words(block(2, 1, 1, np.arange(40000, dtype=np.uint64), 0)).ravel()
+    picks = ga.roulette_pick(cum, u)
+    counts = np.bincount(picks, minlength=5)
+    assert counts[3] == 0 and counts[4] == 0
+    w = 1.0 / (np.array([1.0, 0.5, 0.25]) + 1e-12)
+    assert stats.chisquare(counts[:3], w / w.sum() * u.size).pvalue > 1e-4
+
+
+def test_roulette_all_infinite_falls_back_to_uniform():
+    fit = np.full(6, np.inf, np.float32)
+    cum = ga.roulette_cumulative(fit)
+    u = ga.words(block(3, 1, 1, np.arange(6000, dtype=np.uint64), 0)).ravel()
+    picks = ga.roulette_pick(cum, u)
+    assert picks.min() == 0 and picks.max() == 5
+    assert stats.chisquare(np.bincount(picks, minlength=6)).pvalue > 1e-4
+
+
+@pytest.mark.parametrize("sel", [ga.SELECT_RANKING, ga.SELECT_ROULETTE])
+def test_selection_modes_run_and_keep_the_elite(sel):
+    prob = datagen.small()
+    X, t = prob.X[:400], prob.t[:400]
+    cfg = ga.GAConfig(population=30, seed=0, selection=sel)
+    res = ga.run(X, t, prob.basis, prob.degree, cfg, max_generations=12, target=0.0)
+    h = np.array(res["history"])
+    assert np.all(np.diff(h) <= 1e-7 * h[:-1]) and h[-1] < h[0]
