@@ -17,8 +17,10 @@ a bounded sample on the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,7 +32,35 @@ sys.path.insert(0, ROOT)
 METRIC = "chromosome×pattern evals/s (% MFMA peak); time-to-target MSE, plain vs chosen"
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fitness_f32_scale_traffic.json")
+
+
+def profiled_traffic(summary):
+    """HBM bytes per launch recorded in a committed rocprofv3 summary
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None when
+    the summary is missing or the kernel's sources changed since it was
+    taken."""
+    try:
+        text = open(os.path.join(ROOT, "profiles", summary)).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^(traffic_bytes_per_launch|kernel_sources|kernel_sources_sha256): "
+                             r"(.+)$", text, re.M))
+    if len(fields) != 3:
+        return None
+    h = hashlib.sha256()
+    try:
+        for f in fields["kernel_sources"].split():
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+    except OSError:
+        return None
+    if h.hexdigest()[:16] != fields["kernel_sources_sha256"].strip():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def log(msg):
+    """Progress on stderr; stdout carries only the result line."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(prob, P, seconds=10.0):
@@ -97,18 +127,29 @@ def time_steps(game, steps, warmup):
     return time.perf_counter() - t0
 
 
-def form_bf16(gg, steps, warmup):
+def precision_problem():
+    """The precision problem with its training and validation sets resident
+    on the GPU."""
+    import torch
+    from paper_1304_0597_amd import datagen
+    prob = datagen.precision()
+    dev = torch.device("cuda:0")
+    prob.X_dev, prob.t_dev = torch.from_numpy(prob.X).to(dev), torch.from_numpy(prob.t).to(dev)
+    prob.Xv_dev = torch.from_numpy(prob.X_val).to(dev)
+    prob.tv_dev = torch.from_numpy(prob.t_val).to(dev)
+    return prob
+
+
+def form_bf16(gg, prob, steps, warmup):
     """Precision form: 1,000,000 patterns x 32 features, Chebyshev degree 8
     (257 genes), population 4,096, BF16 operands with FP32 accumulation; the
     error of the BF16 fitness against the float64 re-score of a sample."""
     import torch
-    from paper_1304_0597_amd import datagen
-    prob = datagen.precision()
     P = prob.population
     dev = torch.device("cuda:0")
     cfg = gg.config(basis=prob.basis, degree=prob.degree, population=P, precision=gg.GAME_BF16,
                     seed=0, max_generations=1 << 30, target=-1.0)
-    game = gg.Game(cfg, torch.from_numpy(prob.X).to(dev), torch.from_numpy(prob.t).to(dev))
+    game = gg.Game(cfg, prob.X_dev, prob.t_dev)
     game.init_population()
     stream = torch.cuda.current_stream()
     elapsed = time_steps(game, steps, warmup)
@@ -127,10 +168,72 @@ def form_bf16(gg, steps, warmup):
             "ms_per_step": elapsed * 1e3 / steps, "dtype": "bf16",
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK_TFLOPS,
-                         "traffic": None, "kernel_ms": t_kernel * 1e3, "flops_per_launch": flops},
+                         "traffic": profiled_traffic("fitness_bf16_precision.md"), "kernel_ms": t_kernel * 1e3, "flops_per_launch": flops},
             "error_vs_float64": {"max_rel": float(rel.max()), "median_rel": float(np.median(rel)),
                                  "sample": f"{idx.numel()} chromosomes of the population, "
                                            "float64 re-score on the GPU"}}
+
+
+def _run_to_target(gg, prob, precision, generations, target, surrogate=None):
+    """One run from generation 0 on the precision problem, graph-captured,
+    stopping on the device once its best training error reaches `target`
+    (or after `generations` steps).  Wall time covers init, graph capture and
+    the whole run; the final best is re-scored in float64 on the training and
+    the validation set."""
+    import torch
+    dev = torch.device("cuda:0")
+    P = prob.population
+    cfg = gg.config(basis=prob.basis, degree=prob.degree, population=P, precision=precision,
+                    seed=0, max_generations=generations, target=target)
+    game = gg.Game(cfg, prob.X_dev, prob.t_dev)
+    sur = None
+    if surrogate is not None:
+        sur = gg.Surrogate(gg.surrogate_config(**surrogate), prob.n_genes,
+                           surrogate["oversample"] * (P - cfg.elitism))
+        gg.game_attach_surrogate(game.h, sur.h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    game.init_population()
+    gens, best, err = game.run()
+    elapsed = time.perf_counter() - t0
+    best_dev = torch.from_numpy(best).to(dev).view(1, -1)
+    train64 = float(game.rescore64(best_dev)[0])
+    val64 = float(game.rescore64(best_dev, prob.Xv_dev, prob.tv_dev)[0])
+    res = {"generations": gens, "seconds": elapsed, "reached": bool(train64 <= target * (1 + 1e-3)),
+           "train_mse_fp64": train64, "validation_mse_fp64": val64,
+           "ms_per_generation": elapsed * 1e3 / max(gens, 1)}
+    if sur is not None:
+        st = sur.stats()
+        res["surrogate"] = {"last_rho": st["rho"], "screened_generations": st["screened_total"],
+                            "adam_steps": st["adam_steps"]}
+        sur.close()
+    game.close()
+    return res
+
+
+def form_time_to_target(gg, prob, plain_generations=300, cap=3):
+    """Time to a training-error target on the precision problem, same seed:
+    plain FP32 GAME defines the target (its float64 best error after
+    `plain_generations` generations); plain BF16 and the surrogate-screened
+    BF16 form (network 257-256-256-1, 8x oversampled offspring, exact
+    fallback below rank correlation 0.8) run until they reach it, at most
+    `cap` times as many generations.  Validation error of every final best
+    is reported beside it."""
+    plain = _run_to_target(gg, prob, gg.GAME_FP32, plain_generations, 0.0)
+    target = plain["train_mse_fp64"]
+    plain["reached"] = True
+    bf16 = _run_to_target(gg, prob, gg.GAME_BF16, cap * plain_generations, target)
+    sur_cfg = dict(hidden=256, fp32_operands=0, archive=65536, minibatch=1024, train_steps=4,
+                   lr=1e-3, oversample=8, audit=64, rho_min=0.8, min_archive=4096, seed=0)
+    chosen = _run_to_target(gg, prob, gg.GAME_BF16, cap * plain_generations, target, sur_cfg)
+    return {"workload": "precision problem (1,000,000 x 32, Chebyshev degree 8, population "
+                        "4,096, validation 250,000 patterns), seed 0; target = plain FP32 best "
+                        f"training error after {plain_generations} generations",
+            "target_train_mse": target,
+            "plain_fp32": plain, "plain_bf16": bf16, "surrogate_bf16": chosen,
+            "speedup_chosen_vs_plain": (plain["seconds"] / chosen["seconds"]
+                                        if chosen["reached"] else None),
+            "surrogate_config": sur_cfg}
 
 
 def form_batched(gg, steps, warmup):
@@ -173,7 +276,7 @@ def form_batched(gg, steps, warmup):
             "evals_per_generation": evals,
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-                         "traffic": None, "kernel_ms": t_kernel * 1e3, "flops_per_launch": flops},
+                         "traffic": profiled_traffic("fitness_batch_256runs.md"), "kernel_ms": t_kernel * 1e3, "flops_per_launch": flops},
             "autotune": {"tiles_per_item": tiles, "grid": grid, "items": n_items,
                          "times_ms": tune["times_ms"]}}
 
@@ -186,6 +289,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the BF16, batched and surrogate workloads")
+    ap.add_argument("--no-target", action="store_true",
+                    help="skip the time-to-target comparison (plain FP32 vs surrogate + BF16)")
+    ap.add_argument("--target-generations", type=int, default=300,
+                    help="generations of the plain FP32 run that sets the time-to-target goal")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise kernel of known traffic (256 MiB read, "
                          "256 MiB written per launch) to scale hardware byte counters")
@@ -209,6 +316,7 @@ def main():
     from paper_1304_0597_amd import game as gg
 
     gg.lib()
+    log("scale workload: building inputs")
     prob = datagen.scale()
     P = prob.population
     dev = torch.device("cuda:0")
@@ -221,6 +329,7 @@ def main():
     game.init_population()
     stream = torch.cuda.current_stream()
 
+    log("scale workload: timing generations")
     elapsed = time_steps(game, args.steps, args.warmup)
     st = game.state()
     assert st["stopped"] == 0, "the run stopped inside the timed region"
@@ -235,12 +344,7 @@ def main():
     Kf = prob.n_genes - 1
     flops = 2.0 * Kf * P * prob.n_patterns
     achieved = flops / t_kernel / 1e12
-    traffic = None
-    if os.path.exists(PROFILE_TRAFFIC):
-        try:
-            traffic = json.load(open(PROFILE_TRAFFIC)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = profiled_traffic("fitness_f32_scale.md")
 
     out = {
         "metric": METRIC,
@@ -267,10 +371,19 @@ def main():
     }
     game.close()
     if not args.no_forms:
-        out["forms"] = {"bf16": form_bf16(gg, args.steps, args.warmup),
-                        "batched": form_batched(gg, max(5, args.steps // 5),
-                                                max(2, args.warmup // 5))}
+        log("precision form: building inputs")
+        pprob = precision_problem()
+        log("precision form: timing")
+        forms = {"bf16": form_bf16(gg, pprob, args.steps, args.warmup)}
+        log("batched form: building inputs, autotuning, timing")
+        forms["batched"] = form_batched(gg, max(5, args.steps // 5), max(2, args.warmup // 5))
+        out["forms"] = forms
+        if not args.no_target:
+            log("time to target: plain FP32, plain BF16, surrogate + BF16")
+            out["time_to_target"] = form_time_to_target(gg, pprob, args.target_generations)
+        del pprob
     if not args.no_cpu:
+        log("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(prob, P)
     print(json.dumps(out), flush=True)
 
