@@ -173,3 +173,31 @@ def classification_merit(out, t, threshold: float = 0.5):
         "contamination": fp / (fp + tn) if fp + tn else float("nan"),
         "contamination_of_predicted": fp / (tp + fp) if tp + fp else float("nan"),
     }
+
+
+# ------------------------------------------------ the paper's shared-gene model
+def shared_trig_sums(X, degree: int) -> np.ndarray:
+    """Per-pattern sums of Eq. 9 that do not depend on the genes, computed
+    once per data set (Sec. 4.1 keeps the cos/sin sums out of the training
+    loop): column j-1 is sum_i cos(j f_i), column d+j-1 is sum_i sin(j f_i),
+    j = 1..d; shape [NP, 2d], float64."""
+    X = np.asarray(X, dtype=np.float64)
+    j = np.arange(1, degree + 1, dtype=np.float64)
+    ang = X[:, :, None] * j[None, None, :]                  # [NP, N, d]
+    return np.concatenate([np.cos(ang).sum(axis=1), np.sin(ang).sum(axis=1)], axis=1)
+
+
+def shared_trig_outputs(X, genes, degree: int) -> np.ndarray:
+    """Out of Eq. 9 with the genes shared by all features, chromosome
+    [a_0, a_1..a_d, b_1..b_d] (2d+1 genes, Eq. 7): [NP, P]."""
+    genes = np.atleast_2d(np.asarray(genes, dtype=np.float64))
+    if genes.shape[1] != 2 * degree + 1:
+        raise ValueError("the shared model has 2d+1 genes")
+    S = shared_trig_sums(X, degree)
+    return genes[:, 0][None, :] + S @ genes[:, 1:].T
+
+
+def shared_trig_fitness(X, t, genes, degree: int, error_fn=MSE, R: float = 0.0,
+                        literal_tmse: bool = False) -> np.ndarray:
+    """Fitness of each shared-gene chromosome over the whole set: [P]."""
+    return error_from_outputs(shared_trig_outputs(X, genes, degree), t, error_fn, R, literal_tmse)

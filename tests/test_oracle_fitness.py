@@ -103,6 +103,61 @@ def test_shared_gene_model_is_tied_per_feature_genes():
     np.testing.assert_allclose(out, out_loop, rtol=1e-13, atol=1e-13)
 
 
+def test_shared_trig_model_matches_the_scalar_loop_of_eq9():
+    """The oracle's shared-gene outputs (sums computed once, then a product)
+    against a plain scalar loop over patterns, features and degrees with
+    math.cos / math.sin; and the same model written as the per-feature model
+    with tied genes."""
+    rng = np.random.default_rng(8)
+    N, d, NP, P = 5, 4, 9, 3
+    X = rng.uniform(-3, 3, (NP, N))                   # raw radians, any range
+    G = rng.uniform(-1, 1, (P, 2 * d + 1))
+    loop = np.empty((NP, P))
+    for k in range(NP):
+        for p in range(P):
+            acc = G[p, 0]
+            for i in range(N):
+                for j in range(1, d + 1):
+                    acc += G[p, j] * math.cos(j * X[k, i]) + G[p, d + j] * math.sin(j * X[k, i])
+            loop[k, p] = acc
+    np.testing.assert_allclose(game.shared_trig_outputs(X, G, d), loop, rtol=1e-12, atol=1e-12)
+    tied = np.concatenate([G[:, :1]] + [G[:, 1:]] * N, axis=1)
+    np.testing.assert_allclose(game.outputs(X, tied, game.TRIG, d), loop, rtol=1e-12, atol=1e-12)
+
+
+def test_shared_trig_sums_closed_forms():
+    """sum_i cos(j f_i) over N equal features f is N cos(j f); at f = 0 the
+    cos sums are N and the sin sums 0; with features f and -f the sin sums
+    cancel (odd) and the cos sums double (even)."""
+    d, N = 6, 7
+    S = game.shared_trig_sums(np.zeros((1, N)), d)
+    np.testing.assert_array_equal(S, np.concatenate([np.full((1, d), N), np.zeros((1, d))], 1))
+    f = 0.37
+    S = game.shared_trig_sums(np.full((1, N), f), d)
+    j = np.arange(1, d + 1)
+    np.testing.assert_allclose(S[0, :d], N * np.cos(j * f), rtol=1e-14)
+    np.testing.assert_allclose(S[0, d:], N * np.sin(j * f), rtol=1e-14)
+    S = game.shared_trig_sums(np.array([[f, -f, 1.1, -1.1]]), d)
+    np.testing.assert_allclose(S[0, d:], 0.0, atol=1e-15)
+    np.testing.assert_allclose(S[0, :d], 2 * np.cos(j * f) + 2 * np.cos(j * 1.1), rtol=1e-14)
+
+
+def test_shared_trig_model_is_degree_one_power_model_on_the_sums():
+    """The shared model equals the power expansion of degree 1 over the 2d
+    per-pattern sums taken as features (the way the device evaluates it),
+    with the same chromosome."""
+    rng = np.random.default_rng(9)
+    X = rng.uniform(-1, 1, (50, 11))
+    d = 3
+    G = rng.uniform(-1, 1, (4, 2 * d + 1))
+    t = (rng.random(50) < 0.5).astype(float)
+    Z = game.shared_trig_sums(X, d)
+    np.testing.assert_allclose(game.outputs(Z, G, game.POWER, 1),
+                               game.shared_trig_outputs(X, G, d), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(game.fitness(Z, t, G, game.POWER, 1, game.TMSE, 0.49),
+                               game.shared_trig_fitness(X, t, G, d, game.TMSE, 0.49), rtol=1e-13)
+
+
 def test_num_genes_matches_workload_counts():
     """29 genes for 7 features at degree 4, 161 for 20 at 8, 257 for 32 at 8."""
     assert game.num_genes(game.CHEBYSHEV, 7, 4) == 29
