@@ -223,8 +223,8 @@ def form_time_to_target(gg, prob, plain_generations=300, cap=3):
     target = plain["train_mse_fp64"]
     plain["reached"] = True
     bf16 = _run_to_target(gg, prob, gg.GAME_BF16, cap * plain_generations, target)
-    sur_cfg = dict(hidden=256, fp32_operands=0, archive=65536, minibatch=1024, train_steps=4,
-                   lr=1e-3, oversample=8, audit=64, rho_min=0.8, min_archive=4096, seed=0)
+    sur_cfg = dict(hidden=256, fp32_operands=0, archive=16384, minibatch=1024, train_steps=32,
+                   lr=1e-2, oversample=8, audit=64, rho_min=0.8, min_archive=4096, seed=0)
     chosen = _run_to_target(gg, prob, gg.GAME_BF16, cap * plain_generations, target, sur_cfg)
     return {"workload": "precision problem (1,000,000 x 32, Chebyshev degree 8, population "
                         "4,096, validation 250,000 patterns), seed 0; target = plain FP32 best "
@@ -234,6 +234,59 @@ def form_time_to_target(gg, prob, plain_generations=300, cap=3):
             "speedup_chosen_vs_plain": (plain["seconds"] / chosen["seconds"]
                                         if chosen["reached"] else None),
             "surrogate_config": sur_cfg}
+
+
+# Whole-training wall time (TOT, seconds) of the paper's GPU version for
+# 4,000 generations of the shared-gene polytrigo model, by degree and data
+# size (Table 3; GeForce GT540M, host transfers included).  Context only:
+# another machine, and its time includes host-device transfers.
+PAPER_TABLE3_TOT = {1: (15.00, 240.00, 1870.50, 7680.00), 2: (16.00, 256.00, 1993.55, 8192.00),
+                    4: (19.00, 304.00, 2372.11, 9728.00), 8: (24.00, 384.00, 3006.12, 12288.00)}
+
+
+def form_paper_shaped(gg, generations=4000):
+    """The paper's scaling table on this GPU: the shared-gene polytrigo
+    model (2d+1 genes, Eq. 9) of degree 1, 2, 4 and 8 on the 2,100 x 11
+    binary set replicated to 0.15, 16, 128 and 512 MB of the paper's data
+    size, 23 chromosomes, tournament 4, crossover 0.9, mutation 0.2,
+    elitism 2, TMSE R = 0.49, 4,000 generations.  One run = the cos/sin sums
+    computed once, initialisation and the graph-captured training loop, with
+    the data already in GPU memory."""
+    import torch
+    from paper_1304_0597_amd import datagen
+    base = datagen.paper_shaped()
+    dev = torch.device("cuda:0")
+    Xb = torch.from_numpy(base.X).to(dev)
+    tb = torch.from_numpy(base.t).to(dev)
+    rows = {}
+    for d, paper in PAPER_TABLE3_TOT.items():
+        for size, tot in zip(datagen.PAPER_SIZES_MB, paper):
+            n = datagen.paper_rows(size)
+            reps = -(-n // base.n_patterns)
+            X = Xb.repeat(reps, 1)[:n].contiguous()
+            t = tb.repeat(reps)[:n].contiguous()
+            Z = torch.empty((n, 2 * d), dtype=torch.float32, device=dev)
+            cfg = gg.config(basis=gg.GAME_POWER, degree=1, population=23, tournament_k=4,
+                            elitism=2, p_crossover=0.9, p_mutation=0.2, sigma_mutation=0.1,
+                            error_fn=gg.GAME_TMSE, tmse_R=0.49, seed=0,
+                            max_generations=generations, target=0.0)
+            game = gg.Game(cfg, Z, t)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gg.game_trig_sums(X, d, Z, torch.cuda.current_stream())
+            game.init_population()
+            gens, _, err = game.run()
+            elapsed = time.perf_counter() - t0
+            game.close()
+            rows[f"d{d}_{size:g}MB"] = {"patterns": n, "seconds": elapsed, "generations": gens,
+                                        "best_tmse": err, "paper_tot_seconds": tot,
+                                        "ratio_paper_over_this": tot / elapsed}
+            del X, t, Z
+    return {"workload": "shared-gene polytrigo (Eq. 9), 2,100 x 11 binary set replicated to "
+                        "0.15/16/128/512 MB of the paper's size, population 23, 4,000 "
+                        "generations, TMSE R = 0.49; data resident in GPU memory",
+            "runs": rows,
+            "paper_hardware": "GeForce GT540M (Table 3 TOT, host transfers included)"}
 
 
 def form_batched(gg, steps, warmup):
@@ -378,6 +431,8 @@ def main():
         log("batched form: building inputs, autotuning, timing")
         forms["batched"] = form_batched(gg, max(5, args.steps // 5), max(2, args.warmup // 5))
         out["forms"] = forms
+        log("paper-shaped scaling table: shared-gene polytrigo, 16 runs")
+        out["paper_shaped"] = form_paper_shaped(gg)
         if not args.no_target:
             log("time to target: plain FP32, plain BF16, surrogate + BF16")
             out["time_to_target"] = form_time_to_target(gg, pprob, args.target_generations)

@@ -153,6 +153,44 @@ int game_evaluate(game_t h, const float* X_dev, const float* t_dev, int64_t n_pa
 int game_rescore64(game_t h, const float* X_dev, const float* t_dev, int64_t n_patterns,
                    const float* genes_dev, int32_t n, double* err64_dev);
 
+/* The "run" use case of Sec. 2: the model output Out (Eq. 2) of n
+ * chromosomes genes_dev [n x K] on n_patterns patterns X_dev, into out_dev
+ * [n x n_patterns] float32, chromosome-major.  X_dev NULL means the handle's
+ * own data set (n_patterns is then ignored).  Evaluated in float32 on the
+ * vector ALUs in canonical gene order, whatever cfg.precision is.
+ * 1 <= n <= 65535. */
+int game_predict(game_t h, const float* X_dev, int64_t n_patterns, const float* genes_dev,
+                 int32_t n, float* out_dev);
+
+/* Classification counts of n chromosomes on a labelled set (Sec. 5 figures
+ * of merit): a pattern is predicted as class 1 when Out >= threshold (the
+ * same float32 Out as game_predict) and belongs to class 1 when t > 0.5.
+ * counts_dev [n x 4] int64: true positives, false positives, true
+ * negatives, false negatives.  X_dev/t_dev both NULL means the handle's own
+ * data set. */
+int game_classify(game_t h, const float* X_dev, const float* t_dev, int64_t n_patterns,
+                  const float* genes_dev, int32_t n, float threshold, int64_t* counts_dev);
+
+/* The paper's own model (Eq. 9) shares the genes a_j, b_j over all
+ * features; its per-pattern sums do not depend on the genes and are
+ * computed once per data set (Sec. 4.1).  Z_dev [n_patterns x 2*degree]
+ * float32: column j-1 holds sum_i cos(j x_i), column degree+j-1 holds
+ * sum_i sin(j x_i), j = 1..degree, x_i = X_dev[k * n_features + i] in
+ * radians (any range), evaluated in float64 and rounded once.  A run of
+ * the shared model is a run with basis GAME_POWER, degree 1 on Z_dev as a
+ * data set of 2*degree features: its chromosome is then
+ * [a_0, a_1..a_d, b_1..b_d] (2d+1 genes, Eq. 7).  1 <= degree <= 16.
+ * Queued on hip_stream (NULL: the null stream); stateless. */
+int game_trig_sums(const float* X_dev, int64_t n_patterns, int32_t n_features, int32_t degree,
+                   float* Z_dev, void* hip_stream);
+
+/* Figures of merit of Sec. 5 from host counts[4] (TP, FP, TN, FN):
+ * merit[0] accuracy (TP+TN)/all, merit[1] completeness TP/(TP+FN),
+ * merit[2] contamination FP/(FP+TN) (the fraction of class-0 patterns
+ * classified as class 1), merit[3] FP/(TP+FP) (the other common
+ * convention).  A ratio with a zero denominator is NaN. */
+int game_merit(const int64_t* counts, double* merit);
+
 /* Generation 0: random genes per cfg.init_mode (stream 0, unit =
  * chromosome, block = gene).  Resets the generation counter and stop flag. */
 int game_init_population(game_t h);
@@ -222,10 +260,10 @@ typedef struct game_surrogate_ctx* game_surrogate_t;
 typedef struct {
   int32_t hidden;         /* units per hidden layer (256)                     */
   int32_t fp32_operands;  /* 0: BF16 operands, FP32 accumulation; 1: FP32      */
-  int32_t archive;        /* archive capacity in chromosomes (65536)          */
+  int32_t archive;        /* archive capacity in chromosomes (16384)          */
   int32_t minibatch;      /* rows per Adam step (1024)                        */
-  int32_t train_steps;    /* Adam steps per generation (4)                    */
-  float lr;               /* Adam learning rate (1e-3)                        */
+  int32_t train_steps;    /* Adam steps per generation (32)                   */
+  float lr;               /* Adam learning rate (1e-2)                        */
   int32_t oversample;     /* children generated per kept child (8)            */
   int32_t audit;          /* children scored exactly per generation (64)      */
   float rho_min;          /* rank correlation needed to screen (0.8)          */

@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "libgame.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 SOURCES = ["fitness_f32.hip", "fitness_bf16.hip", "rescore64.hip", "batch.hip", "mlp.hip",
-           "ga.hip", "runtime.hip"]
+           "ga.hip", "predict.hip", "trig_sums.hip", "runtime.hip"]
 COMMON = ["-O3", f"--offload-arch={ARCH}", "-std=c++20", "-fPIC",
           # keep the compiler from emitting packed-FP32 VALU instructions
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -12,6 +12,14 @@ constexpr int kMaxDegree = 16;
 constexpr int kMaxPopulation = 8192;
 constexpr int kMaxGenes = 4097;
 constexpr int kMaxSplits = 64;
+// A single run's partial sums hold max(Ppad * kMaxSplits, kSplitCapacity)
+// doubles, so a launch over few chromosome tiles may cut the patterns into
+// more splits (up to kSplitCapacity / ld_partial) and still fill the GPU.
+constexpr int kSplitCapacity = 65536;
+inline int max_splits(int ld_partial) {
+  const int c = kSplitCapacity / (ld_partial < 1 ? 1 : ld_partial);
+  return c > kMaxSplits ? c : kMaxSplits;
+}
 
 // Fitness tile geometry: a workgroup of 4 waves covers 256 patterns x 64
 // chromosomes; each wave 64 patterns (two 32-row MFMA blocks) x 64
@@ -75,6 +83,22 @@ hipError_t launch_fitness_bf16(const FitArgs& a, int basis, int degree, hipStrea
 constexpr int kMaxTileCols = 128;
 
 // Float64 re-score of n chromosomes over a data set.
+// Per-pattern cos/sin sums of the shared-gene model: Z [NP x 2d].
+hipError_t launch_trig_sums(const float* X, int64_t NP, int N, int d, float* Z, hipStream_t s);
+
+// Outputs (counts == nullptr) or classification counts of n chromosomes.
+struct PredictArgs {
+  const float* X;           // [NP x N]
+  const float* t;           // [NP] class labels (classification)
+  const float* genes;       // [n x K]
+  int64_t NP;
+  int32_t N, K, degree, n;
+  float threshold;          // predicted class 1 when Out >= threshold
+  float* out;               // [n x NP] (prediction)
+  int64_t* counts;          // [n x 4]: TP, FP, TN, FN (classification)
+};
+hipError_t launch_predict(const PredictArgs& a, int basis, hipStream_t s);
+
 struct Rescore64Args {
   const float* X;
   const float* t;
@@ -228,10 +252,15 @@ struct GemmArgs {
   int32_t M, N, K;
   int32_t act;              // 0 none, 1 GELU, 2 times GELU'(aux)
   const int32_t* skip;      // when set and nonzero the launch does nothing
+  float* rowsum;            // when set: rowsum[m] = sum_k A(m, k) in float32
+  int32_t k_split;          // > 1: K cut into k_split ranges summed in a fixed order
+  float* part;              // k_split > 1: [k_split][M][N] partial products
+  float* part_rs;           // k_split > 1 with rowsum: [k_split][M] partial row sums
 };
+// Number of K ranges for a product whose K (a minibatch) is long and whose
+// M x N is small: 128 or more K values per range, at most 8 ranges.
+inline int gemm_k_split(int K) { return K >= 256 ? (K / 128 < 8 ? K / 128 : 8) : 1; }
 hipError_t launch_gemm(const GemmArgs& g, bool bf16, hipStream_t s);
-hipError_t launch_colsum(const float* A, int M, int N, int ld, float* out, const int32_t* skip,
-                         hipStream_t s);
 hipError_t launch_out_grad(const float* y, const float* t, int B, const float* w3, const float* Z2,
                            int H, float* dy, float* dZ2, const int32_t* skip, hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
@@ -245,7 +274,8 @@ struct SurrogateState {
   float rho;                // Spearman correlation of the last audit
   int32_t use;              // 1 when this generation's offspring are screened
   int32_t screened;         // generations screened so far
-  int32_t pad[6];
+  int32_t skip;             // 1 when the candidates need no full scoring (stopped or not used)
+  int32_t pad[5];
 };
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                        SurrogateState* st, const int32_t* skip, hipStream_t s);
@@ -270,14 +300,18 @@ hipError_t launch_archive_stats(const float* target, SurrogateState* st, const R
 hipError_t launch_sample_minibatch(const float* genes, const float* target, int32_t K,
                                    const SurrogateState* st, const RunState* run, uint64_t seed,
                                    int32_t step, int32_t B, float* Xb, float* tb, hipStream_t s);
-hipError_t launch_audit_pick(const float* cand, const float* pred, int32_t C, int32_t K,
-                             const RunState* run, uint64_t seed, int32_t A, float* genes,
-                             float* pred_out, hipStream_t s);
+hipError_t launch_audit_pick(const float* cand, int32_t C, int32_t K, const RunState* run,
+                             uint64_t seed, int32_t A, float* genes, hipStream_t s);
 hipError_t launch_spearman_gate(const float* pred, const float* exact, int32_t A, float rho_min,
                                 int32_t min_archive, const RunState* run, SurrogateState* st,
                                 hipStream_t s);
-hipError_t launch_rank_large(const float* v, int32_t n, int32_t* rank, const RunState* run,
-                             hipStream_t s);
+// Rank by (value, index) of up to ~10^6 values: chunks of kSortChunk keys
+// sorted in LDS, then each value's rank summed over binary searches of the
+// sorted chunks.  sorted holds sort_chunks(n) * kSortChunk keys.
+constexpr int kSortChunk = 8192;
+inline int sort_chunks(int64_t n) { return (int)((n + kSortChunk - 1) / kSortChunk); }
+hipError_t launch_rank_sorted(const float* v, int32_t n, uint64_t* sorted, int32_t* rank,
+                              const int32_t* skip, hipStream_t s);
 hipError_t launch_gather_next(const float* cand, const int32_t* rank, int32_t C, int32_t K,
                               int32_t E, int32_t P, const RunState* run, const SurrogateState* st,
                               float* pop0, float* pop1, hipStream_t s);

@@ -22,6 +22,17 @@
 // Tiles: a workgroup covers 256 patterns x 128 chromosomes; each wave 64
 // patterns (two 32-row blocks) x 128 chromosomes (four 32-column blocks),
 // eight 32x32 accumulators, so each generated A fragment feeds four MFMAs.
+//
+// Features and targets (XL variant, feature count a multiple of 4 and
+// 16-byte aligned rows): each wave copies its own 64 rows of the next tile
+// from HBM straight into LDS (global_load_lds_dwordx4, four features per
+// lane and instruction; one dword per lane for the targets) while it
+// computes the current tile, into the other of two buffers; nothing is
+// shared between waves, so only the wave's own vmcnt wait guards a buffer.
+// The copy of a tile is issued a whole tile (17 K-steps of MFMAs for 32
+// features at degree 8) before its use, which hides the HBM latency that a
+// one-group-ahead register prefetch leaves exposed.  Other shapes load
+// features into registers one group ahead.
 #include <utility>
 
 #include "basis.h"
@@ -62,7 +73,13 @@ __device__ __forceinline__ void split3(float x, bf16x8& p) {
 // 8 bf16) plus 16 bytes so that rows start 4 banks apart.
 __host__ __device__ constexpr int bf16_row_bytes(int ksteps) { return ksteps * 32 + 16; }
 
-template <int BASIS, int D>
+// Per-wave LDS bytes of one XL buffer: features [N/4][64 rows][4 floats],
+// then the 64 targets.
+__host__ __device__ constexpr int xl_buffer_bytes(int n_features) {
+  return (n_features / 4) * 64 * 16 + 64 * 4;
+}
+
+template <int BASIS, int D, bool XL>
 __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a) {
   constexpr int G = group_size(D);         // sub-features per lane half per group
   constexpr int KS = G * D / 8;            // K-steps per group
@@ -167,8 +184,44 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
   const bool tube = a.error_fn == 2 || a.error_fn == 3;
   const float thr = a.R;
 
+  // XL: this wave's two buffers after the gene rows.
+  const int XB = xl_buffer_bytes(N);
+  unsigned char* xl_base = lds_raw + kCols * RS + wave * 2 * XB;
+  auto xl_issue = [&](int tile, int buf) {
+    const int64_t r = min((int64_t)tile * kTileRows + wave * 64 + lane, NP - 1);
+    const float* src = a.X + r * N;
+    unsigned char* dst = xl_base + buf * XB;
+    for (int q = 0; q < N / 4; ++q)
+      __builtin_amdgcn_global_load_lds((const void*)(src + 4 * q),
+                                       (__attribute__((address_space(3))) void*)(dst + q * 1024),
+                                       16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void*)(a.t + r),
+                                     (__attribute__((address_space(3))) void*)(dst + (N / 4) * 1024),
+                                     4, 0, 0);
+  };
+  // x of group g from XL buffer buf (rows rb*32 + m of this wave).
+  auto xl_read = [&](int buf, int g, float (&xo)[2][G]) {
+    const unsigned char* src = xl_base + buf * XB;
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const int qi = g * G + i;
+      const int u = 2 * qi + h;
+      const bool fvalid = BASIS == 3 ? (qi < N) : (u < a.U);
+      const int f = fvalid ? (BASIS == 3 ? qi : u) : 0;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const float* p = reinterpret_cast<const float*>(src + (f >> 2) * 1024 + (rb * 32 + m) * 16) + (f & 3);
+        xo[rb][i] = fvalid ? *p : 0.f;
+      }
+    }
+  };
+
   float xn[2][G];
-  if (tile_begin < tile_end) load_x((int64_t)tile_begin * kTileRows + wave * 64, 0, xn);
+  if constexpr (XL) {
+    if (tile_begin < tile_end) xl_issue(tile_begin, 0);
+  } else {
+    if (tile_begin < tile_end) load_x((int64_t)tile_begin * kTileRows + wave * 64, 0, xn);
+  }
   const int n_groups = a.Q;
 
   // B fragments of this lane for the four column blocks at a K-step's byte
@@ -185,6 +238,15 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
 
   for (int tile = tile_begin; tile < tile_end; ++tile) {
     const int64_t row0 = (int64_t)tile * kTileRows + wave * 64;
+    const int xbuf = (tile - tile_begin) & 1;
+    if constexpr (XL) {
+      // This tile's copy (issued a tile ago) has landed; the other buffer's
+      // reads all completed in the previous tile, so it takes the next copy.
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+      __asm__ __volatile__("" ::: "memory");
+      if (tile + 1 < tile_end) xl_issue(tile + 1, xbuf ^ 1);
+      xl_read(xbuf, 0, xn);
+    }
     // Bias K-step: accumulators start at a_0 - t_k, exactly.
     f32x16 acc[2][4];
 #pragma unroll
@@ -194,6 +256,9 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
         abias[0] = (__bf16)1.f;
         abias[1] = (__bf16)1.f;
         abias[2] = (__bf16)1.f;
+      } else if constexpr (XL) {
+        const float* tl = reinterpret_cast<const float*>(xl_base + xbuf * XB + (N / 4) * 1024);
+        split3(-tl[rb * 32 + m], abias);
       } else {
         const int64_t r = row0 + rb * 32 + m;
         split3(-a.t[r < NP ? r : NP - 1], abias);
@@ -218,8 +283,12 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
           for (int i = 0; i < G; ++i) x[rb][i] = xn[rb][i];
-        if (g + 1 < n_groups) load_x(row0, g + 1, xn);
-        else if (tile + 1 < tile_end) load_x(row0 + kTileRows, 0, xn);
+        if constexpr (XL) {
+          if (g + 1 < n_groups) xl_read(xbuf, g + 1, xn);
+        } else {
+          if (g + 1 < n_groups) load_x(row0, g + 1, xn);
+          else if (tile + 1 < tile_end) load_x(row0 + kTileRows, 0, xn);
+        }
 
         const int kbase = (g - g_begin) * KS * 32;
         bf16x8 av[2][2];
@@ -323,12 +392,21 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
   }
 }
 
-size_t fitness_bf16_lds_bytes(const FitArgs& a, int degree) {
+size_t fitness_bf16_lds_bytes(const FitArgs& a, int degree, bool xl) {
   const int G = group_size(degree);
   const int KS = G * degree / 8;
-  const size_t w = (size_t)128 * bf16_row_bytes(a.pairs_per_chunk * KS);
+  const size_t w = (size_t)128 * bf16_row_bytes(a.pairs_per_chunk * KS) +
+                   (xl ? (size_t)4 * 2 * xl_buffer_bytes(a.N) : 0);
   const size_t red = 4 * 128 * sizeof(double);
   return w > red ? w : red;
+}
+
+// The LDS copy path needs whole 16-byte feature quads per row, 16-byte
+// aligned rows and room for the buffers next to the genes.
+static bool use_xl(const FitArgs& a, int degree) {
+  constexpr size_t kLdsPerCu = 160 * 1024;
+  return a.N % 4 == 0 && ((uintptr_t)a.X & 15) == 0 && ((uintptr_t)a.t & 3) == 0 &&
+         fitness_bf16_lds_bytes(a, degree, true) <= kLdsPerCu;
 }
 
 // Plan: Q = number of groups of 2G sub-features; pairs_per_chunk = groups
@@ -348,7 +426,7 @@ void plan_fitness_bf16(FitArgs& a, int degree, int basis) {
   a.n_tiles = (int32_t)((a.NP + kTileRows - 1) / kTileRows);
   const int target = 512;
   int splits = (target + a.n_ctiles - 1) / a.n_ctiles;
-  if (splits > kMaxSplits) splits = kMaxSplits;
+  if (splits > max_splits(a.ld_partial)) splits = max_splits(a.ld_partial);
   if (splits > a.n_tiles) splits = a.n_tiles;
   if (splits < 1) splits = 1;
   a.tiles_per_split = (a.n_tiles + splits - 1) / splits;
@@ -356,17 +434,22 @@ void plan_fitness_bf16(FitArgs& a, int degree, int basis) {
   a.xcd_remap = ((a.n_ctiles * a.n_splits) % 8) == 0 ? 1 : 0;
 }
 
-template <int BASIS, int D>
-static hipError_t launch_one(const FitArgs& a, hipStream_t s) {
-  const size_t lds = fitness_bf16_lds_bytes(a, D);
+template <int BASIS, int D, bool XL>
+static hipError_t launch_variant(const FitArgs& a, hipStream_t s) {
+  const size_t lds = fitness_bf16_lds_bytes(a, D, XL);
   const int grid = a.n_ctiles * a.n_splits;
   if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute((const void*)fitness_bf16_kernel<BASIS, D>,
+    const hipError_t e = hipFuncSetAttribute((const void*)fitness_bf16_kernel<BASIS, D, XL>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((fitness_bf16_kernel<BASIS, D>), dim3(grid), dim3(kFitThreads), lds, s, a);
+  hipLaunchKernelGGL((fitness_bf16_kernel<BASIS, D, XL>), dim3(grid), dim3(kFitThreads), lds, s, a);
   return hipGetLastError();
+}
+
+template <int BASIS, int D>
+static hipError_t launch_one(const FitArgs& a, hipStream_t s) {
+  return use_xl(a, D) ? launch_variant<BASIS, D, true>(a, s) : launch_variant<BASIS, D, false>(a, s);
 }
 
 template <int BASIS>

@@ -280,7 +280,7 @@ void plan_fitness(FitArgs& a, int degree, int basis) {
   // Aim at two resident workgroups per CU on 256 CUs in one wave of blocks.
   const int target = 512;
   int splits = (target + a.n_ctiles - 1) / a.n_ctiles;
-  if (splits > kMaxSplits) splits = kMaxSplits;
+  if (splits > max_splits(a.ld_partial)) splits = max_splits(a.ld_partial);
   if (splits > a.n_tiles) splits = a.n_tiles;
   if (splits < 1) splits = 1;
   a.tiles_per_split = (a.n_tiles + splits - 1) / splits;

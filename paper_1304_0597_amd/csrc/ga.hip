@@ -658,11 +658,10 @@ hipError_t launch_sample_minibatch(const float* genes, const float* target, int3
 }
 
 // Audit sample: A candidates drawn uniformly with replacement (key
-// (seed, 3), counter (generation, 0x7FFFFFFF, a, 0)); their genes and
-// predictions are copied out for exact scoring.
-__global__ void audit_pick_kernel(const float* cand, const float* pred, int C, int K,
-                                  const RunState* run, uint64_t seed, int A, float* genes,
-                                  float* pred_out) {
+// (seed, 3), counter (generation, 0x7FFFFFFF, a, 0)); their genes are copied
+// out to be scored by the network and exactly.
+__global__ void audit_pick_kernel(const float* cand, int C, int K, const RunState* run,
+                                  uint64_t seed, int A, float* genes) {
   if (run->stop) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)A * K) return;
@@ -670,15 +669,13 @@ __global__ void audit_pick_kernel(const float* cand, const float* pred, int C, i
   const U64x4 r = draw(seed, 3, (uint64_t)run->gen, 0x7FFFFFFFull, (uint64_t)a);
   const int idx = (int)(((r.o0 & 0xFFFFFFFFull) * (uint64_t)C) >> 32);
   genes[i] = cand[(int64_t)idx * K + g];
-  if (g == 0) pred_out[a] = pred[idx];
 }
 
-hipError_t launch_audit_pick(const float* cand, const float* pred, int32_t C, int32_t K,
-                             const RunState* run, uint64_t seed, int32_t A, float* genes,
-                             float* pred_out, hipStream_t s) {
+hipError_t launch_audit_pick(const float* cand, int32_t C, int32_t K, const RunState* run,
+                             uint64_t seed, int32_t A, float* genes, hipStream_t s) {
   const int64_t n = (int64_t)A * K;
   hipLaunchKernelGGL(audit_pick_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cand,
-                     pred, C, K, run, seed, A, genes, pred_out);
+                     C, K, run, seed, A, genes);
   return hipGetLastError();
 }
 
@@ -692,7 +689,10 @@ __global__ __launch_bounds__(1024) void spearman_gate_kernel(const float* pred, 
                                                              SurrogateState* st) {
   __shared__ float ra[1024], rb[1024];
   __shared__ double sab[1024], saa[1024], sbb[1024];
-  if (run->stop) return;
+  if (run->stop) {
+    if (threadIdx.x == 0) st->skip = 1;
+    return;
+  }
   const int i = threadIdx.x;
   if (i < A) {
     const float p = rank_key_value(pred[i]), e = rank_key_value(exact[i]);
@@ -726,6 +726,7 @@ __global__ __launch_bounds__(1024) void spearman_gate_kernel(const float* pred, 
     st->rho = rho;
     const int use = (st->count >= min_archive && rho >= rho_min) ? 1 : 0;
     st->use = use;
+    st->skip = 1 - use;
     st->screened += use;
   }
 }
@@ -738,40 +739,66 @@ hipError_t launch_spearman_gate(const float* pred, const float* exact, int32_t A
   return hipGetLastError();
 }
 
-// Rank of every value by (value, index) for up to a few hundred thousand
-// values: each workgroup ranks 64 of them against all keys, staged through
-// LDS 4096 at a time and counted by 16 waves.
-constexpr int kLargeChunk = 4096;
-__global__ __launch_bounds__(1024) void rank_large_kernel(const float* v, int n, int32_t* rank,
-                                                          const RunState* run) {
-  __shared__ uint64_t keys[kLargeChunk];
-  __shared__ uint32_t cnt[1024];
-  if (run && run->stop) return;
-  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int part = threadIdx.x >> 6;                      // 16 parts
-  const uint64_t ke = e < n ? rank_key(v[e], e) : ~0ull;
-  uint32_t c = 0;
-  for (int c0 = 0; c0 < n; c0 += kLargeChunk) {
-    const int m = min(kLargeChunk, n - c0);
-    __syncthreads();
-    for (int j = threadIdx.x; j < m; j += blockDim.x) keys[j] = rank_key(v[c0 + j], c0 + j);
-    __syncthreads();
-    const int per = (m + 15) / 16;
-    const int j0 = part * per, j1 = min(j0 + per, m);
-    for (int j = j0; j < j1; ++j) c += keys[j] < ke ? 1u : 0u;
+// Rank of every value by (value, index).  Each workgroup bitonic-sorts one
+// chunk of kSortChunk keys in LDS (padding keys ~0 sort last and are larger
+// than any real key); then each value's rank is the sum over chunks of the
+// number of keys below its own, found by binary search.  Keys are unique, so
+// the ranks are a permutation of 0..n-1.
+__global__ __launch_bounds__(1024) void chunk_sort_kernel(const float* v, int n, uint64_t* sorted,
+                                                          const int32_t* skip) {
+  __shared__ uint64_t keys[kSortChunk];
+  if (skip && *skip) return;
+  const int base = blockIdx.x * kSortChunk;
+  for (int j = threadIdx.x; j < kSortChunk; j += blockDim.x) {
+    const int e = base + j;
+    keys[j] = e < n ? rank_key(v[e], e) : ~0ull;
   }
-  cnt[threadIdx.x] = c;
   __syncthreads();
-  if (threadIdx.x < 64 && e < n) {
-    uint32_t t = 0;
-    for (int k = 0; k < 16; ++k) t += cnt[k * 64 + threadIdx.x];
-    rank[e] = (int32_t)t;
+  for (int k = 2; k <= kSortChunk; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < kSortChunk / 2; t += blockDim.x) {
+        const int lo = 2 * t - (t & (j - 1));     // partner index lo + j has bit j set
+        const uint64_t a = keys[lo], b = keys[lo + j];
+        if ((a > b) == ((lo & k) == 0)) {
+          keys[lo] = b;
+          keys[lo + j] = a;
+        }
+      }
+      __syncthreads();
+    }
   }
+  for (int j = threadIdx.x; j < kSortChunk; j += blockDim.x) sorted[base + j] = keys[j];
 }
 
-hipError_t launch_rank_large(const float* v, int32_t n, int32_t* rank, const RunState* run,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(rank_large_kernel, dim3((n + 63) / 64), dim3(1024), 0, s, v, n, rank, run);
+__global__ void merge_rank_kernel(const float* v, int n, const uint64_t* sorted, int n_chunks,
+                                  int32_t* rank, const int32_t* skip) {
+  if (skip && *skip) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const uint64_t key = rank_key(v[e], e);
+  int r = 0;
+  for (int c = 0; c < n_chunks; ++c) {
+    const uint64_t* s = sorted + (int64_t)c * kSortChunk;
+    int lo = 0, hi = kSortChunk;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s[mid] < key) lo = mid + 1;
+      else hi = mid;
+    }
+    r += lo;
+  }
+  rank[e] = r;
+}
+
+hipError_t launch_rank_sorted(const float* v, int32_t n, uint64_t* sorted, int32_t* rank,
+                              const int32_t* skip, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int nc = sort_chunks(n);
+  hipLaunchKernelGGL(chunk_sort_kernel, dim3(nc), dim3(1024), 0, s, v, n, sorted, skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(merge_rank_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n,
+                     sorted, nc, rank, skip);
   return hipGetLastError();
 }
 

@@ -2,14 +2,21 @@
 // hidden layers (genes -> standardised log error), trained on the GPU.
 //
 // gemm_kernel computes C[m][n] = sum_k A(m,k) B(n,k) with arbitrary element
-// strides for A and B (so forward products, weight gradients X^T dZ and
+// strides for A and B (so forward products, weight gradients dZ^T X and
 // input gradients dZ W all use one kernel), on MFMA: BF16 operands with FP32
 // accumulation (v_mfma_f32_32x32x16_bf16), or FP32 operands
 // (v_mfma_f32_32x32x2_f32) for a full-precision mode.  Epilogues: + bias[n],
 // then identity, GELU (optionally storing the pre-activation), or
 // multiplication by GELU'(aux[m][n]) (the backward of a GELU layer).
 // A workgroup of 4 waves computes a 64x64 tile of C from 64x32 slices of A
-// and B staged in LDS; out-of-range rows, columns and k read as zero.
+// and B staged in LDS; out-of-range rows, columns and k read as zero.  Each
+// operand is staged with consecutive threads along its unit-stride index,
+// so the global reads are coalesced whichever way the operand is laid out.
+// Optionally the workgroups of the first column tile also sum the rows of
+// A over k (the bias gradient of a layer comes with its weight gradient).
+// Long-K products with a small M x N (weight gradients over a minibatch)
+// split K over blockIdx.z; the ranges' partial results are added in a fixed
+// order by gemm_reduce_kernel, so results do not depend on scheduling.
 #include <math.h>
 
 #include "common.h"
@@ -29,6 +36,26 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
   return 0.5f * (1.f + erff(z * kSqrtHalf)) + z * kInvSqrt2Pi * expf(-0.5f * z * z);
 }
 
+// Stages a 64 x 32 slice X(r0 + r, k0 + c) into S[r][c]; rows >= R or
+// k >= K read as zero.  Threads run along c when the k stride is 1, else
+// along r.
+__device__ __forceinline__ void stage_slice(float (*S)[kGemmK + 1], const float* X, int64_t ld_r,
+                                            int64_t ld_k, int r0, int R, int k0, int K) {
+  if (ld_k == 1) {
+    for (int i = threadIdx.x; i < kGemmTile * kGemmK; i += 256) {
+      const int r = i / kGemmK, c = i % kGemmK;
+      const int gr = r0 + r, gk = k0 + c;
+      S[r][c] = (gr < R && gk < K) ? X[(int64_t)gr * ld_r + gk] : 0.f;
+    }
+  } else {
+    for (int i = threadIdx.x; i < kGemmTile * kGemmK; i += 256) {
+      const int r = i % kGemmTile, c = i / kGemmTile;
+      const int gr = r0 + r, gk = k0 + c;
+      S[r][c] = (gr < R && gk < K) ? X[(int64_t)gr * ld_r + (int64_t)gk * ld_k] : 0.f;
+    }
+  }
+}
+
 template <bool BF16>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   __shared__ float As[kGemmTile][kGemmK + 1];
@@ -39,15 +66,21 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   const int wm = wave >> 1, wn = wave & 1;       // 2 x 2 waves of 32 x 32
   const int m0 = blockIdx.y * kGemmTile, n0 = blockIdx.x * kGemmTile;
   const int l32 = lane & 31, h = lane >> 5;
+  // K range of this split (whole slices; the last range may be short).
+  const int kc = ((g.K + g.k_split - 1) / g.k_split + kGemmK - 1) / kGemmK * kGemmK;
+  const int kb = blockIdx.z * kc, ke = min(g.K, kb + kc);
+  const bool do_rs = g.rowsum && blockIdx.x == 0;
+  const int rs_r = threadIdx.x >> 2, rs_q = threadIdx.x & 3;   // 4 threads per row
+  float rs = 0.f;
   f32x16 acc = f32x16{};
-  for (int k0 = 0; k0 < g.K; k0 += kGemmK) {
-    for (int i = threadIdx.x; i < kGemmTile * kGemmK; i += 256) {
-      const int r = i / kGemmK, c = i % kGemmK;
-      const int m = m0 + r, n = n0 + r, k = k0 + c;
-      As[r][c] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.lda_m + (int64_t)k * g.lda_k] : 0.f;
-      Bs[r][c] = (n < g.N && k < g.K) ? g.B[(int64_t)n * g.ldb_n + (int64_t)k * g.ldb_k] : 0.f;
-    }
+  for (int k0 = kb; k0 < ke; k0 += kGemmK) {
+    stage_slice(As, g.A, g.lda_m, g.lda_k, m0, g.M, k0, ke);
+    stage_slice(Bs, g.B, g.ldb_n, g.ldb_k, n0, g.N, k0, ke);
     __syncthreads();
+    if (do_rs) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) rs += As[rs_r][rs_q * 8 + c];
+    }
     const int am = wm * 32 + l32, bn = wn * 32 + l32;
     if constexpr (BF16) {
 #pragma unroll
@@ -67,8 +100,27 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     }
     __syncthreads();
   }
+  if (do_rs) {
+    // The row's 4 partial sums sit in 4 consecutive lanes: fixed-order pairs.
+    rs += __shfl_xor(rs, 1);
+    rs += __shfl_xor(rs, 2);
+    const int m = m0 + rs_r;
+    if (rs_q == 0 && m < g.M) {
+      if (g.k_split > 1) g.part_rs[(int64_t)blockIdx.z * g.M + m] = rs;
+      else g.rowsum[m] = rs;
+    }
+  }
   const int n = n0 + wn * 32 + l32;
   if (n >= g.N) return;
+  if (g.k_split > 1) {
+    float* P = g.part + (int64_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int m = m0 + wm * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+      if (m < g.M) P[(int64_t)m * g.N + n] = acc[i];
+    }
+    return;
+  }
   const float bias = g.bias ? g.bias[n] : 0.f;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
@@ -86,27 +138,37 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   }
 }
 
-hipError_t launch_gemm(const GemmArgs& g, bool bf16, hipStream_t s) {
-  const dim3 grid((g.N + kGemmTile - 1) / kGemmTile, (g.M + kGemmTile - 1) / kGemmTile);
+// Split-K results: C[m][n] = sum over ranges in order; row sums likewise.
+__global__ void gemm_reduce_kernel(GemmArgs g) {
+  if (g.skip && *g.skip) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t MN = (int64_t)g.M * g.N;
+  if (i < MN) {
+    float s = 0.f;
+    for (int z = 0; z < g.k_split; ++z) s += g.part[(int64_t)z * MN + i];
+    const int m = (int)(i / g.N), n = (int)(i - (int64_t)m * g.N);
+    g.C[(int64_t)m * g.ldc + n] = s;
+  } else if (g.rowsum && i < MN + g.M) {
+    const int m = (int)(i - MN);
+    float s = 0.f;
+    for (int z = 0; z < g.k_split; ++z) s += g.part_rs[(int64_t)z * g.M + m];
+    g.rowsum[m] = s;
+  }
+}
+
+hipError_t launch_gemm(const GemmArgs& g0, bool bf16, hipStream_t s) {
+  GemmArgs g = g0;
+  if (g.k_split < 1) g.k_split = 1;
+  if (g.k_split > 1 && (g.bias || g.act || !g.part || (g.rowsum && !g.part_rs)))
+    return hipErrorInvalidValue;   // split-K products carry no epilogue
+  const dim3 grid((g.N + kGemmTile - 1) / kGemmTile, (g.M + kGemmTile - 1) / kGemmTile,
+                  g.k_split);
   if (bf16) hipLaunchKernelGGL(gemm_kernel<true>, grid, dim3(256), 0, s, g);
   else hipLaunchKernelGGL(gemm_kernel<false>, grid, dim3(256), 0, s, g);
-  return hipGetLastError();
-}
-
-// out[n] = sum_m A[m * ld + n] in a fixed order (column sums: bias gradients).
-__global__ void colsum_kernel(const float* A, int M, int N, int ld, float* out,
-                              const int32_t* skip) {
-  if (skip && *skip) return;
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  float s = 0.f;
-  for (int m = 0; m < M; ++m) s += A[(int64_t)m * ld + n];
-  out[n] = s;
-}
-
-hipError_t launch_colsum(const float* A, int M, int N, int ld, float* out, const int32_t* skip,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, s, A, M, N, ld, out, skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || g.k_split == 1) return e;
+  const int64_t n = (int64_t)g.M * g.N + (g.rowsum ? g.M : 0);
+  hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 

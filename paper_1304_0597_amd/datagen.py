@@ -150,6 +150,23 @@ def precision(seed=0, n=1_000_000):
     return binary_problem("precision", n, 32, CHEBYSHEV, 8, 4096, 1000, seed)
 
 
+def paper_shaped(seed=0):
+    """The shape of the paper's knowledge base: 2,100 patterns x 11 features
+    with a 0/1 label (here from a random degree-4 trigonometric teacher with
+    5% flips), for the shared-gene polytrigo model with 23 chromosomes
+    (2N + 1) and 4,000 generations.  Larger sets replicate its rows."""
+    return binary_problem("paper-shaped", 2100, 11, TRIG, 4, 23, 4000, seed)
+
+
+# Data sizes of the paper's scaling table and the rows that reproduce them
+# by replicating the 2,100-row set (0.15 MB holds the 2,100 rows).
+PAPER_SIZES_MB = (0.15, 16, 128, 512)
+
+
+def paper_rows(size_mb: float) -> int:
+    return int(round(2100 * size_mb / 0.15))
+
+
 @dataclasses.dataclass
 class RunShape:
     n_patterns: int

@@ -65,6 +65,11 @@ _SIGS = {
                                 c_void_p]),
     "game_rescore64": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int32,
                                  c_void_p]),
+    "game_predict": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int32, c_void_p]),
+    "game_classify": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int32, c_float,
+                                c_void_p]),
+    "game_merit": (c_int32, [c_void_p, c_void_p]),
+    "game_trig_sums": (c_int32, [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p]),
     "game_init_population": (c_int32, [c_void_p]),
     "game_step": (c_int32, [c_void_p]),
     "game_run": (c_int32, [c_void_p, c_int32, c_double, POINTER(c_int32), c_void_p,
@@ -217,6 +222,42 @@ def game_rescore64(h, X, t, genes, n, err64) -> None:
                                 _ptr(genes, torch.float32), n, _ptr(err64, torch.float64)))
 
 
+def game_predict(h, X, genes, n, out) -> None:
+    """X None -> the handle's own data set."""
+    import torch
+    n_patterns = X.shape[0] if X is not None else 0
+    _check(lib().game_predict(h, _ptr(X, torch.float32), n_patterns, _ptr(genes, torch.float32),
+                              n, _ptr(out, torch.float32)))
+
+
+def game_classify(h, X, t, genes, n, threshold, counts) -> None:
+    """X, t None -> the handle's own data set."""
+    import torch
+    n_patterns = X.shape[0] if X is not None else 0
+    _check(lib().game_classify(h, _ptr(X, torch.float32), _ptr(t, torch.float32), n_patterns,
+                               _ptr(genes, torch.float32), n, threshold,
+                               _ptr(counts, torch.int64)))
+
+
+def game_trig_sums(X, degree: int, Z=None, stream=None):
+    """Per-pattern cos/sin sums of the shared-gene model: Z [NP x 2*degree]."""
+    import torch
+    if Z is None:
+        Z = torch.empty((X.shape[0], 2 * degree), dtype=torch.float32, device=X.device)
+    _check(lib().game_trig_sums(_ptr(X, torch.float32), X.shape[0], X.shape[1], degree,
+                                _ptr(Z, torch.float32), _stream(stream)))
+    return Z
+
+
+def game_merit(counts) -> dict:
+    """counts: four integers (TP, FP, TN, FN)."""
+    c = (ctypes.c_int64 * 4)(*[int(v) for v in counts])
+    m = (c_double * 4)()
+    _check(lib().game_merit(c, m))
+    return {"accuracy": m[0], "completeness": m[1], "contamination": m[2],
+            "contamination_of_predicted": m[3]}
+
+
 def game_init_population(h) -> None:
     _check(lib().game_init_population(h))
 
@@ -323,6 +364,20 @@ class Game:
         out = torch.empty(genes.shape[0], dtype=torch.float64, device=genes.device)
         game_rescore64(self.h, X, t, genes, genes.shape[0], out)
         return out
+
+    def predict(self, genes, X=None):
+        import torch
+        n_patterns = X.shape[0] if X is not None else self.X.shape[0]
+        out = torch.empty((genes.shape[0], n_patterns), dtype=torch.float32, device=genes.device)
+        game_predict(self.h, X, genes, genes.shape[0], out)
+        return out
+
+    def classify(self, genes, X=None, t=None, threshold=0.5):
+        """Counts [n x 4] (TP, FP, TN, FN) on the device."""
+        import torch
+        counts = torch.empty((genes.shape[0], 4), dtype=torch.int64, device=genes.device)
+        game_classify(self.h, X, t, genes, genes.shape[0], threshold, counts)
+        return counts
 
     def init_population(self):
         game_init_population(self.h)

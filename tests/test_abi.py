@@ -137,3 +137,29 @@ def test_batch_rejects_invalid_runs_without_gpu():
     descs[1].cfg.degree = 0
     assert game.lib().game_batch_workspace_size(descs, 2) == 0
     assert game.lib().game_batch_workspace_size(descs, 0) == 0
+
+
+@pytest.mark.parametrize("counts", [(10, 2, 30, 5), (0, 0, 5, 0), (3, 0, 0, 0), (0, 4, 0, 6),
+                                    (0, 0, 0, 0)])
+def test_merit_follows_the_oracle_definitions(counts):
+    """game_merit (host arithmetic on the four counts) against the oracle's
+    figures of merit of outputs and labels built to give those counts."""
+    import numpy as np
+    from oracle import game as og
+    tp, fp, tn, fn = counts
+    out = np.array([1.0] * tp + [1.0] * fp + [0.0] * tn + [0.0] * fn)
+    t = np.array([1.0] * tp + [0.0] * fp + [0.0] * tn + [1.0] * fn)
+    got = game.game_merit(counts)
+    if sum(counts) == 0:
+        assert all(np.isnan(v) for v in got.values())
+        return
+    ref = og.classification_merit(out, t)
+    for k, v in ref.items():
+        assert (np.isnan(v) and np.isnan(got[k])) or got[k] == pytest.approx(v, rel=1e-15), k
+
+
+def test_predict_null_handle_fails_without_gpu():
+    L = game.lib()
+    assert L.game_predict(None, None, 0, None, 1, None) == game.GAME_EINVAL
+    assert L.game_classify(None, None, None, 0, None, 1, ctypes.c_float(0.5), None) == game.GAME_EINVAL
+    assert L.game_merit(None, None) == game.GAME_EINVAL

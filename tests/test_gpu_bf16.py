@@ -58,8 +58,13 @@ def problem(NP, N, d, P, basis, seed):
     return X, t, W
 
 
+# Feature counts that are multiples of 4 take the LDS-copy path for features
+# and targets (several tiles per workgroup in the 70,000-row case, so both
+# buffers alternate; ragged last tiles); the others load into registers.
 SHAPES = [(1, 1, 1, 1), (300, 3, 8, 130), (1000, 7, 4, 50), (777, 9, 3, 129), (513, 5, 16, 64),
-          (2049, 33, 8, 200), (600, 20, 5, 257), (256, 64, 2, 128)]
+          (2049, 33, 8, 200), (600, 20, 5, 257), (256, 64, 2, 128), (1000, 8, 4, 50),
+          (3001, 12, 7, 130), (515, 4, 16, 64), (4099, 32, 8, 129), (70000, 16, 3, 40),
+          (300001, 4, 2, 10)]
 
 
 @pytest.mark.parametrize("basis", [0, 1, 2, 3])

@@ -59,6 +59,8 @@ SHAPES = [
     (1, 1, 1, 1), (7, 3, 2, 5), (255, 4, 3, 63), (256, 5, 4, 64), (257, 7, 4, 65),
     (2000, 7, 4, 50), (3001, 20, 8, 130), (777, 9, 5, 129), (600, 1, 16, 3),
     (513, 64, 2, 100), (300, 33, 10, 70), (1100, 300, 1, 66),
+    # few chromosomes over many patterns: hundreds of pattern splits
+    (300001, 4, 2, 10),
 ]
 
 

@@ -65,7 +65,8 @@ def test_init_matches_oracle(gg):
 
 
 @pytest.mark.parametrize("fp32", [True, False])
-@pytest.mark.parametrize("n_in,H,B", [(257, 256, 256), (29, 64, 100), (161, 32, 77)])
+@pytest.mark.parametrize("n_in,H,B", [(257, 256, 256), (29, 64, 100), (161, 32, 77), (40, 64, 1024),
+                                      (33, 96, 1100)])
 def test_forward_and_gradients_match_oracle(gg, fp32, n_in, H, B):
     rng = np.random.default_rng(n_in + H + B)
     s = make(gg, n_in, fp32, H=H, minibatch=B, max_batch=B)
@@ -202,3 +203,28 @@ def test_trained_surrogate_gains_over_plain(gg):
         s.close()
         gains.append(plain / screened)
     assert np.median(gains) > 1.0, gains
+
+
+@pytest.mark.parametrize("population", [128, 1100])
+def test_screened_offspring_are_in_predicted_order(gg, population):
+    """Always screening (rho_min below any correlation): the offspring slots
+    hold candidates in ascending predicted error.  The network is unchanged
+    between the screening and the check (training happens at the start of a
+    generation), so re-predicting the new offspring must give a sorted
+    sequence; with population 1100 the 8x oversampled candidates (8,784)
+    span two sort chunks."""
+    prob = datagen.regression_problem("surrogate-order", 3000, 10, 0, 6, population, 40, seed=4)
+    g = _game(gg, prob)
+    E = g.cfg.elitism
+    s = make(gg, prob.n_genes, True, H=32, minibatch=128, max_batch=8 * (population - E),
+             rho_min=-1.0, min_archive=0, audit=16)
+    gg.game_attach_surrogate(g.h, s.h)
+    g.init_population()
+    for _ in range(3):
+        g.step()
+        pop, _ = g.population()
+        y = s.predict(pop[E:].contiguous()).cpu().numpy()
+        assert np.all(np.diff(y) >= 0)
+    assert s.stats()["screened_total"] == 3
+    g.close()
+    s.close()
