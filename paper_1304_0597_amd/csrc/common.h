@@ -7,6 +7,27 @@
 
 namespace game {
 
+// Sum over splits of chromosome i's partials, called by all 64 lanes of a
+// wave: lane l adds splits l, l+64, ... in order, then a butterfly adds the
+// lane sums.  Partner lanes add the same two values (a + b == b + a), so
+// every lane ends with the same, scheduling-independent value.
+__device__ __forceinline__ double wave_split_sum(const double* partial, int64_t ld, int n_splits,
+                                                 int i) {
+  double s = 0.0;
+  for (int k = (int)(threadIdx.x & 63); k < n_splits; k += 64) s += partial[(int64_t)k * ld + i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  return s;
+}
+
+// Error of a split sum: mean over the NP patterns, root for RMSE, NaN -> +inf.
+__device__ __forceinline__ double error_from_sum(double s, int64_t NP, int error_fn) {
+  double v = s / (double)NP;
+  if (error_fn == 1) v = sqrt(v);
+  if (isnan(v)) v = INFINITY;
+  return v;
+}
+
+
 constexpr int kWave = 64;
 constexpr int kMaxDegree = 16;
 constexpr int kMaxPopulation = 8192;
@@ -164,6 +185,9 @@ struct RankArgs {
   RunState* state;
 };
 hipError_t launch_finish_rank(const RankArgs& a, hipStream_t s);
+// fit64/fit32 of every chromosome from the split partials (one wave per
+// chromosome, wave_split_sum order); runs before finish_rank.
+hipError_t launch_reduce_fitness(const RankArgs& a, hipStream_t s);
 constexpr int kRankThreads = 1024;
 constexpr int kRankPerBlock = 64;
 hipError_t launch_set_state(RunState* st, int32_t gen, int32_t max_gen, double target,
@@ -236,6 +260,7 @@ struct BatchArgs {
 };
 hipError_t launch_fitness_batch(const BatchArgs& a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_finish_rank_batch(const BatchArgs& a, hipStream_t s);
+hipError_t launch_reduce_fitness_batch(const BatchArgs& a, hipStream_t s);
 hipError_t launch_ga_next_batch(const BatchArgs& a, hipStream_t s);
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
 hipError_t launch_roulette_cum_batch(const BatchArgs& a, hipStream_t s);
@@ -261,13 +286,14 @@ struct GemmArgs {
 // M x N is small: 128 or more K values per range, at most 8 ranges.
 inline int gemm_k_split(int K) { return K >= 256 ? (K / 128 < 8 ? K / 128 : 8) : 1; }
 hipError_t launch_gemm(const GemmArgs& g, bool bf16, hipStream_t s);
-hipError_t launch_out_grad(const float* y, const float* t, int B, const float* w3, const float* Z2,
-                           int H, float* dy, float* dZ2, const int32_t* skip, hipStream_t s);
+// Output layer (and with t set, its backward); see out_layer_kernel.
+hipError_t launch_out_layer(const float* H2, const float* w3, const float* b3, int B, int H,
+                            float* y, const float* t, const float* Z2, float* dy, float* dZ2,
+                            int32_t* step, const int32_t* skip, hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
 
 struct SurrogateState {
   int32_t step;             // Adam steps taken
-  float c1, c2;             // Adam bias corrections of the current step
   int32_t head;             // archive ring position of the next append
   int32_t count;            // archive entries
   float mean, inv_std;      // standardisation of the archive targets
@@ -275,7 +301,7 @@ struct SurrogateState {
   int32_t use;              // 1 when this generation's offspring are screened
   int32_t screened;         // generations screened so far
   int32_t skip;             // 1 when the candidates need no full scoring (stopped or not used)
-  int32_t pad[5];
+  int32_t pad[7];
 };
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                        SurrogateState* st, const int32_t* skip, hipStream_t s);

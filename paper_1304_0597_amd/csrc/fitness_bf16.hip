@@ -211,7 +211,8 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb) {
         const float* p = reinterpret_cast<const float*>(src + (f >> 2) * 1024 + (rb * 32 + m) * 16) + (f & 3);
-        xo[rb][i] = fvalid ? *p : 0.f;
+        const float v = *p;                  // f is clamped: always in the buffer
+        xo[rb][i] = fvalid ? v : 0.f;
       }
     }
   };
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
 #pragma unroll
           for (int i = 0; i < G; ++i) x[rb][i] = xn[rb][i];
         if constexpr (XL) {
-          if (g + 1 < n_groups) xl_read(xbuf, g + 1, xn);
+          xl_read(xbuf, g + 1 < n_groups ? g + 1 : g, xn);   // no branch in the group body
         } else {
           if (g + 1 < n_groups) load_x(row0, g + 1, xn);
           else if (tile + 1 < tile_end) load_x(row0 + kTileRows, 0, xn);
@@ -330,6 +331,28 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
         [&]<int... P>(std::integer_sequence<int, P...>) {
           (value(std::integral_constant<int, P>{}), ...);
         }(std::make_integer_sequence<int, G * D>{});
+#ifndef GAME_BF16_SCHED
+#define GAME_BF16_SCHED 0
+#endif
+        if constexpr (XL && GAME_BF16_SCHED == 1) {
+          // Interleave: each MFMA followed by a share of the recurrence,
+          // conversion and LDS work of the next K-step.
+#pragma unroll
+          for (int q = 0; q < 8 * KS; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
+            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);   // VALU
+          }
+        } else if constexpr (XL && GAME_BF16_SCHED == 2) {
+#pragma unroll
+          for (int q = 0; q < 8 * KS; ++q) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
+            if (q % 2 == 0) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          }
+        } else if constexpr (XL && GAME_BF16_SCHED == 3) {
+          __builtin_amdgcn_iglp_opt(1);
+        }
       }
     }
 

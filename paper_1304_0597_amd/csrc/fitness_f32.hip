@@ -288,25 +288,23 @@ void plan_fitness(FitArgs& a, int degree, int basis) {
   a.xcd_remap = ((a.n_ctiles * a.n_splits) % 8) == 0 ? 1 : 0;
 }
 
-// fitness[i] = sum_s partial[s][i] / NP (fixed order), RMSE takes the root;
-// NaN becomes +inf.
+// fitness[i] = sum_s partial[s][i] / NP (wave_split_sum order), RMSE takes
+// the root; NaN becomes +inf.  One wave per chromosome.
 __global__ void finish_kernel(const double* __restrict__ partial, int32_t ld, int32_t n,
                               int32_t n_splits, int64_t NP, int32_t error_fn, float* f32,
                               double* f64) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= n) return;
-  double s = 0.0;
-  for (int k = 0; k < n_splits; ++k) s += partial[(int64_t)k * ld + i];
-  double v = s / (double)NP;
-  if (error_fn == 1) v = sqrt(v);
-  if (isnan(v)) v = INFINITY;
-  if (f32) f32[i] = (float)v;
-  if (f64) f64[i] = v;
+  const double v = error_from_sum(wave_split_sum(partial, ld, n_splits, i), NP, error_fn);
+  if ((threadIdx.x & 63) == 0) {
+    if (f32) f32[i] = (float)v;
+    if (f64) f64[i] = v;
+  }
 }
 
 hipError_t launch_finish(const double* partial, int32_t ld, int32_t n, int32_t n_splits,
                          int64_t NP, int32_t error_fn, float* f32, double* f64, hipStream_t s) {
-  hipLaunchKernelGGL(finish_kernel, dim3((n + 255) / 256), dim3(256), 0, s, partial, ld, n,
+  hipLaunchKernelGGL(finish_kernel, dim3((n + 3) / 4), dim3(256), 0, s, partial, ld, n,
                      n_splits, NP, error_fn, f32, f64);
   return hipGetLastError();
 }

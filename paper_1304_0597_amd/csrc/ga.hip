@@ -159,18 +159,36 @@ hipError_t launch_rank(const float* fit, int32_t n, int32_t* order, hipStream_t 
   return hipGetLastError();
 }
 
-__device__ __forceinline__ double error_of(const RankArgs& a, int i) {
-  double s = 0.0;
-  for (int k = 0; k < a.n_splits; ++k) s += a.partial[(int64_t)k * a.ld_partial + i];
-  double v = s / (double)a.NP;
-  if (a.error_fn == 1) v = sqrt(v);
-  if (isnan(v)) v = INFINITY;
-  return v;
+// Errors of the 64 chromosomes [blk*64, blk*64+64) from their split
+// partials, one wave per chromosome (4 waves per workgroup).
+__device__ void reduce_fitness_body(const RankArgs& a, int blk) {
+  if (a.state->stop_seen) return;
+  const int waves = blockDim.x >> 6;
+  for (int j = (int)(threadIdx.x >> 6); j < kRankPerBlock; j += waves) {
+    const int i = blk * kRankPerBlock + j;
+    if (i >= a.P) break;
+    const double v = error_from_sum(wave_split_sum(a.partial, a.ld_partial, a.n_splits, i), a.NP,
+                                    a.error_fn);
+    if ((threadIdx.x & 63) == 0) {
+      a.fit64[i] = v;
+      a.fit32[i] = (float)v;
+    }
+  }
 }
 
-// Evaluation epilogue of one generation: errors from the float64 partials
-// (the same fixed-order sums in every workgroup), rank order, best
-// chromosome, stop test and the generation counter.  The stop flag that
+__global__ __launch_bounds__(256) void reduce_fitness_kernel(RankArgs a) {
+  reduce_fitness_body(a, blockIdx.x);
+}
+
+hipError_t launch_reduce_fitness(const RankArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_fitness_kernel, dim3((a.P + kRankPerBlock - 1) / kRankPerBlock),
+                     dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// Evaluation epilogue of one generation: rank order of the errors that
+// reduce_fitness wrote, best chromosome, stop test and the generation
+// counter.  The stop flag that
 // decides whether this launch works is the one the generation's fitness
 // launch recorded, so a workgroup that sets the flag cannot make another
 // workgroup of the same launch skip its share.
@@ -180,22 +198,14 @@ __device__ void finish_rank_body(const RankArgs& a, int blk, uint64_t* keys, uin
   if (st->stop_seen) return;
   const int P = a.P;
   const int lo = blk * kRankPerBlock;
-  for (int i = threadIdx.x; i < P; i += blockDim.x) {
-    const double v = error_of(a, i);
-    const float f = (float)v;
-    keys[i] = rank_key(f, i);
-    if (i >= lo && i < lo + kRankPerBlock) {
-      a.fit32[i] = f;
-      a.fit64[i] = v;
-    }
-  }
+  for (int i = threadIdx.x; i < P; i += blockDim.x) keys[i] = rank_key(a.fit32[i], i);
   __syncthreads();
   const int e = lo + (threadIdx.x % kRankPerBlock);
   const int r = count_rank(keys, P, e, cnt);
   if (r < 0) return;
   a.order[r] = e;
   if (r == 0) {
-    const double v = error_of(a, e);
+    const double v = a.fit64[e];
     const int gen = st->gen;
     st->best = e;
     st->best_err = v;
@@ -446,6 +456,17 @@ __global__ __launch_bounds__(kRankThreads) void finish_rank_batch_kernel(BatchAr
   const int r = a.rank_block_run[blockIdx.x];
   const BatchRun& run = a.runs[r];
   finish_rank_body(rank_args_of(run), blockIdx.x - run.rank_block0, keys, cnt);
+}
+
+__global__ __launch_bounds__(256) void reduce_fitness_batch_kernel(BatchArgs a) {
+  const int r = a.rank_block_run[blockIdx.x];
+  const BatchRun& run = a.runs[r];
+  reduce_fitness_body(rank_args_of(run), blockIdx.x - run.rank_block0);
+}
+
+hipError_t launch_reduce_fitness_batch(const BatchArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_fitness_batch_kernel, dim3(a.n_rank_blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_finish_rank_batch(const BatchArgs& a, hipStream_t s) {

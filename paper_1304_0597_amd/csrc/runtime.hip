@@ -322,8 +322,11 @@ SurParams split_params(const game_surrogate_ctx* s, float* base) {
 }
 
 // Forward over n rows of X [n x n_in]; stores Z1/Z2 when given (training).
+// Forward pass over n rows of X; with t set (training) the output layer
+// also writes dy and dZ2 for the loss mean((y - t)^2).
 int sur_forward(game_surrogate_ctx* s, const float* X, int n, float* Z1, float* H1, float* Z2,
-                float* H2, float* y, const int32_t* skip, hipStream_t st) {
+                float* H2, float* y, const int32_t* skip, hipStream_t st,
+                const float* t = nullptr, int32_t* step = nullptr) {
   const bool bf16 = !s->cfg.fp32_operands;
   const SurParams p = split_params(s, s->params);
   const int H = s->H, ni = s->n_in;
@@ -331,20 +334,22 @@ int sur_forward(game_surrogate_ctx* s, const float* X, int n, float* Z1, float* 
                        bf16, st));
   GAME_HIP(launch_gemm(gemm(H1, H, 1, p.W2, H, 1, H2, H, n, H, H, p.b2, 1, Z2, nullptr, 0, skip),
                        bf16, st));
-  GAME_HIP(launch_gemm(gemm(H2, H, 1, p.w3, H, 1, y, 1, n, 1, H, p.b3, 0, nullptr, nullptr, 0, skip),
-                       bf16, st));
+  GAME_HIP(launch_out_layer(H2, p.w3, p.b3, n, H, y, t, Z2, t ? s->dy : nullptr,
+                            t ? s->dZ2 : nullptr, step, skip, st));
   return GAME_OK;
 }
 
-// Gradients of mean((y - t)^2) over the n rows in s->Xb / s->tb into s->grads.
-int sur_gradients(game_surrogate_ctx* s, int n, const int32_t* skip, hipStream_t st) {
+// Gradients of mean((y - t)^2) over the n rows in s->Xb / s->tb into
+// s->grads; for_adam: this is a training step (advances the step count).
+int sur_gradients(game_surrogate_ctx* s, int n, const int32_t* skip, hipStream_t st,
+                  bool for_adam) {
   const bool bf16 = !s->cfg.fp32_operands;
   const int H = s->H, ni = s->n_in;
-  int rc = sur_forward(s, s->Xb, n, s->Z1, s->H1, s->Z2, s->H2, s->y, skip, st);
+  int rc = sur_forward(s, s->Xb, n, s->Z1, s->H1, s->Z2, s->H2, s->y, skip, st, s->tb,
+                       for_adam ? &s->st->step : nullptr);
   if (rc) return rc;
   const SurParams p = split_params(s, s->params);
   const SurParams g = split_params(s, s->grads);
-  GAME_HIP(launch_out_grad(s->y, s->tb, n, p.w3, s->Z2, H, s->dy, s->dZ2, skip, st));
   // Weight gradients sum over the n minibatch rows: split K when n is long
   // (n <= cfg.minibatch, for which the partial buffers are sized).  Each
   // bias gradient is the row sum of the product's A operand.
@@ -397,7 +402,7 @@ int enqueue_screening(game_ctx* h, hipStream_t s) {
   for (int step = 0; step < c.train_steps; ++step) {
     GAME_HIP(launch_sample_minibatch(sr->arch_genes, sr->arch_target, K, sr->st, h->state, c.seed,
                                      step, c.minibatch, sr->Xb, sr->tb, s));
-    int rc = sur_gradients(sr, c.minibatch, stop, s);
+    int rc = sur_gradients(sr, c.minibatch, stop, s, true);
     if (rc) return rc;
     GAME_HIP(launch_adam(sr->params, sr->grads, sr->m, sr->v, sr->n_params, c.lr, sr->st, stop, s));
   }
@@ -458,6 +463,7 @@ int enqueue_step(game_ctx* h, hipStream_t s) {
   ra.fit64 = h->fit64;
   ra.order = h->order;
   ra.state = h->state;
+  GAME_HIP(launch_reduce_fitness(ra, s));
   GAME_HIP(launch_finish_rank(ra, s));
   if (h->cfg.selection == GAME_ROULETTE)
     GAME_HIP(launch_roulette_cum(h->fit32, h->cfg.population, h->cum, &h->state->stop, s));
@@ -997,7 +1003,7 @@ int game_surrogate_gradients(game_surrogate_t s, const float* genes, const float
   GAME_HIP(hipMemcpyAsync(s->Xb, genes, sizeof(float) * n * s->n_in, hipMemcpyDeviceToDevice,
                           s->stream));
   GAME_HIP(hipMemcpyAsync(s->tb, target, sizeof(float) * n, hipMemcpyDeviceToDevice, s->stream));
-  int rc = sur_gradients(s, n, nullptr, s->stream);
+  int rc = sur_gradients(s, n, nullptr, s->stream, false);
   if (rc) return rc;
   GAME_HIP(hipMemcpyAsync(grads, s->grads, sizeof(float) * s->n_params, hipMemcpyDeviceToDevice,
                           s->stream));
@@ -1013,7 +1019,7 @@ int game_surrogate_train_step(game_surrogate_t s, const float* genes, const floa
   GAME_HIP(hipMemcpyAsync(s->Xb, genes, sizeof(float) * n * s->n_in, hipMemcpyDeviceToDevice,
                           s->stream));
   GAME_HIP(hipMemcpyAsync(s->tb, target, sizeof(float) * n, hipMemcpyDeviceToDevice, s->stream));
-  int rc = sur_gradients(s, n, nullptr, s->stream);
+  int rc = sur_gradients(s, n, nullptr, s->stream, true);
   if (rc) return rc;
   GAME_HIP(launch_adam(s->params, s->grads, s->m, s->v, s->n_params, s->cfg.lr, s->st, nullptr,
                        s->stream));
@@ -1196,6 +1202,7 @@ BatchArgs batch_args(const game_batch_ctx* b) {
 int enqueue_batch_step(game_batch_ctx* b, hipStream_t s) {
   const BatchArgs a = batch_args(b);
   GAME_HIP(launch_fitness_batch(a, b->lds, s));
+  GAME_HIP(launch_reduce_fitness_batch(a, s));
   GAME_HIP(launch_finish_rank_batch(a, s));
   if (b->any_roulette) GAME_HIP(launch_roulette_cum_batch(a, s));
   GAME_HIP(launch_ga_next_batch(a, s));

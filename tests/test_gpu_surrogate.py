@@ -162,7 +162,7 @@ def test_fallback_reproduces_the_plain_run(gg):
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
     st = s.stats()
     assert st["screened_total"] == 0 and st["archive_count"] == 6 * 128
-    assert st["adam_steps"] == 6 * 4
+    assert st["adam_steps"] == 6 * s.cfg.train_steps
     for g in (g1, g2):
         g.close()
     s.close()
