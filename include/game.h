@@ -202,7 +202,10 @@ int game_init_population(game_t h);
 int game_step(game_t h);
 
 /* Runs steps until a stop criterion holds, with the loop captured in a HIP
- * graph (no host round trip per generation); synchronises the stream.
+ * graph (no host round trip per generation); with a surrogate attached the
+ * generations are queued on the stream in batches of 8 with a look at the
+ * stop flag between batches instead (its few hundred short launches per
+ * generation run faster that way).  Synchronises the stream.
  * max_generations < 0 and target < 0 keep the configured values.  Outputs
  * (each may be NULL): the number of evolution steps applied since the
  * last init/set, the best chromosome [K] and its float64 error. */

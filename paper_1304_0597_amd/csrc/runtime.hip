@@ -726,7 +726,20 @@ int game_run(game_t h, int32_t max_gen, double target, int32_t* gens_done, float
   RunState st{};
   GAME_HIP(hipMemcpyAsync(&st, h->state, sizeof st, hipMemcpyDeviceToHost, h->stream));
   GAME_HIP(hipStreamSynchronize(h->stream));
-  if (!h->graph) {
+  if (h->sur) {
+    // A screened generation is a few hundred short launches; the stream runs
+    // them back to back faster than a graph replays them, so generations
+    // are queued directly, 8 at a time, with a look at the stop flag between
+    // batches (steps queued after the stop do nothing).
+    while (!st.stop) {
+      for (int i = 0; i < 8; ++i) {
+        const int rc = enqueue_step(h, h->stream);
+        if (rc) return rc;
+      }
+      GAME_HIP(hipMemcpyAsync(&st, h->state, sizeof st, hipMemcpyDeviceToHost, h->stream));
+      GAME_HIP(hipStreamSynchronize(h->stream));
+    }
+  } else if (!h->graph) {
     // Capture a fixed number of generations once; every kernel reads the
     // generation counter and the stop flag from device memory, so the same
     // graph serves every replay and does nothing once stopped.
@@ -749,7 +762,7 @@ int game_run(game_t h, int32_t max_gen, double target, int32_t* gens_done, float
     }
     h->graph_steps = steps;
   }
-  if (!st.stop) {
+  if (!st.stop && !h->sur) {
     const int64_t evals = (int64_t)h->cfg.max_generations - st.gen + 1;
     const int64_t launches = evals <= 0 ? 1 : (evals + h->graph_steps - 1) / h->graph_steps;
     for (int64_t i = 0; i < launches; ++i) GAME_HIP(hipGraphLaunch(h->graph, h->stream));

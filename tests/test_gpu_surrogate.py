@@ -228,3 +228,30 @@ def test_screened_offspring_are_in_predicted_order(gg, population):
     assert s.stats()["screened_total"] == 3
     g.close()
     s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_screened_run_equals_screened_steps(gg, precision):
+    """game_run with a surrogate attached (always screening) ends where the
+    same number of single steps ends, bit for bit, network included."""
+    prob = datagen.regression_problem("surrogate-run", 20000, 16, 0, 6, 512, 40, seed=2)
+    P, G = prob.population, 20
+    out = []
+    for mode in ("run", "steps"):
+        g = _game(gg, prob, precision=precision, seed=1)
+        s = make(gg, prob.n_genes, False, H=64, minibatch=256, max_batch=8 * (P - 2),
+                 train_steps=8, min_archive=512, rho_min=-1.0, archive=4096)
+        gg.game_attach_surrogate(g.h, s.h)
+        g.init_population()
+        if mode == "run":
+            gens, _, _ = g.run(max_generations=G)
+            assert gens == G
+        else:
+            for _ in range(G):
+                g.step()
+        pop, _ = g.population()
+        out.append((pop.cpu().numpy().view(np.uint32).copy(),
+                    s.params().cpu().numpy().view(np.uint32).copy()))
+        g.close()
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
