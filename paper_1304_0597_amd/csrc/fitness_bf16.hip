@@ -19,20 +19,24 @@
 // chain is split between lanes.  Genes are staged in LDS in that order as
 // bfloat16.
 //
-// Tiles: a workgroup covers 256 patterns x 128 chromosomes; each wave 64
-// patterns (two 32-row blocks) x 128 chromosomes (four 32-column blocks),
+// Tiles: a workgroup covers 128 chromosomes; each wave takes 64 patterns (two
+// 32-row blocks) of a 256-row tile x 128 chromosomes (four 32-column blocks):
 // eight 32x32 accumulators, so each generated A fragment feeds four MFMAs.
+// With eight waves (see bf16_waves) waves 0-3 take the even tiles of the
+// split and waves 4-7 the odd ones, two waves per SIMD.
+//
+// Pipelining: within a group, the eight MFMAs of K-step k are issued in
+// pairs, each pair followed by the B fragments of K-step k+1 for that column
+// block and two of K-step k+1's A values (the last K-step generates the next
+// group's first one), with scheduling barriers holding that order.
 //
 // Features and targets (XL variant, feature count a multiple of 4 and
-// 16-byte aligned rows): each wave copies its own 64 rows of the next tile
-// from HBM straight into LDS (global_load_lds_dwordx4, four features per
-// lane and instruction; one dword per lane for the targets) while it
-// computes the current tile, into the other of two buffers; nothing is
-// shared between waves, so only the wave's own vmcnt wait guards a buffer.
-// The copy of a tile is issued a whole tile (17 K-steps of MFMAs for 32
-// features at degree 8) before its use, which hides the HBM latency that a
-// one-group-ahead register prefetch leaves exposed.  Other shapes load
-// features into registers one group ahead.
+// 16-byte aligned rows): each wave copies the 64 rows of its next tile from
+// HBM straight into its own LDS buffer (global_load_lds_dwordx4, four
+// features per lane and instruction; one dword per lane for the targets) as
+// soon as it has read the current tile's last features, two groups before
+// the tile ends; only the wave's own vmcnt wait guards the buffer.  Other
+// shapes load features into registers one group ahead.
 #include <utility>
 
 #include "basis.h"
@@ -79,10 +83,21 @@ __host__ __device__ constexpr int xl_buffer_bytes(int n_features) {
   return (n_features / 4) * 64 * 16 + 64 * 4;
 }
 
+// Waves per workgroup.  Eight (two per SIMD, 256 registers each) when a
+// group holds at most 4 sub-features per lane half, so that everything stays
+// in registers: waves 0-3 take the even tiles of the split and waves 4-7 the
+// odd ones, and one wave's vector work and memory waits run under the other
+// wave's MFMAs.  Larger groups need more registers than two waves per SIMD
+// allow and run four waves over consecutive tiles.
+__host__ __device__ constexpr int bf16_waves(int degree) { return group_size(degree) <= 4 ? 8 : 4; }
+
 template <int BASIS, int D, bool XL>
-__global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a) {
+__global__ __launch_bounds__(64 * bf16_waves(D), 1) void fitness_bf16_kernel(FitArgs a) {
   constexpr int G = group_size(D);         // sub-features per lane half per group
   constexpr int KS = G * D / 8;            // K-steps per group
+  constexpr int NW = bf16_waves(D);        // waves per workgroup
+  constexpr int NT = 64 * NW;              // threads per workgroup
+  constexpr int TS = NW / 4;               // tiles in flight per workgroup (tile stride)
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   if (a.stop) {
     const int32_t stopped = *a.stop;
@@ -94,6 +109,8 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  const int wq = wave & 3;                 // 64-row slice within a tile
+  const int wg = wave >> 2;                // tile offset (0..TS-1) this wave takes
   const int m = lane & 31;
   const int h = lane >> 5;
 
@@ -133,7 +150,7 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
   // p%D + 1); it goes to byte (kstep*32 + hh*16 + (p%8)*2) of the row.
   auto stage = [&](int chunk) {
     const int per_row = gpc * 2 * G * D;   // values per chromosome row
-    for (int idx = threadIdx.x; idx < kCols * per_row; idx += kFitThreads) {
+    for (int idx = threadIdx.x; idx < kCols * per_row; idx += NT) {
       const int c = idx / per_row;
       const int r = idx - c * per_row;
       const int gl = r / (2 * G * D);      // group within the chunk
@@ -186,11 +203,11 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
 
   // XL: this wave's two buffers after the gene rows.
   const int XB = xl_buffer_bytes(N);
-  unsigned char* xl_base = lds_raw + kCols * RS + wave * 2 * XB;
-  auto xl_issue = [&](int tile, int buf) {
-    const int64_t r = min((int64_t)tile * kTileRows + wave * 64 + lane, NP - 1);
+  unsigned char* xl_base = lds_raw + kCols * RS + wave * XB;
+  auto xl_issue = [&](int tile) {
+    const int64_t r = min((int64_t)tile * kTileRows + wq * 64 + lane, NP - 1);
     const float* src = a.X + r * N;
-    unsigned char* dst = xl_base + buf * XB;
+    unsigned char* dst = xl_base;
     for (int q = 0; q < N / 4; ++q)
       __builtin_amdgcn_global_load_lds((const void*)(src + 4 * q),
                                        (__attribute__((address_space(3))) void*)(dst + q * 1024),
@@ -199,9 +216,9 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
                                      (__attribute__((address_space(3))) void*)(dst + (N / 4) * 1024),
                                      4, 0, 0);
   };
-  // x of group g from XL buffer buf (rows rb*32 + m of this wave).
-  auto xl_read = [&](int buf, int g, float (&xo)[2][G]) {
-    const unsigned char* src = xl_base + buf * XB;
+  // x of group g from this wave's XL buffer (rows rb*32 + m of the slice).
+  auto xl_read = [&](int g, float (&xo)[2][G]) {
+    const unsigned char* src = xl_base;
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       const int qi = g * G + i;
@@ -217,11 +234,11 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
     }
   };
 
-  float xn[2][G];
+  float xt[2][G];                          // next tile's first group (register path)
   if constexpr (XL) {
-    if (tile_begin < tile_end) xl_issue(tile_begin, 0);
+    if (tile_begin + wg < tile_end) xl_issue(tile_begin + wg);
   } else {
-    if (tile_begin < tile_end) load_x((int64_t)tile_begin * kTileRows + wave * 64, 0, xn);
+    if (tile_begin + wg < tile_end) load_x((int64_t)(tile_begin + wg) * kTileRows + wq * 64, 0, xt);
   }
   const int n_groups = a.Q;
 
@@ -234,21 +251,68 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
     for (int cb = 0; cb < 4; ++cb)
       bo[cb] = *reinterpret_cast<const bf16x8*>(wrow + cb * 32 * RS + kbyte);
   };
-  bf16x8 bcur[4];
-  if (a.n_chunks == 1) load_b(0, bcur);
+  // bq[k & 1]: B fragments of K-step k of the group; av[k & 1][rb]: A
+  // fragments likewise (with an odd number of K-steps per group, the next
+  // group's first fragments are moved to index 0 at the group's end).
+  bf16x8 bq[2][4];
+  if (a.n_chunks == 1) load_b(0, bq[0]);
+  bf16x8 av[2][2];
 
-  for (int tile = tile_begin; tile < tile_end; ++tile) {
-    const int64_t row0 = (int64_t)tile * kTileRows + wave * 64;
-    const int xbuf = (tile - tile_begin) & 1;
+  // Value p of a group (sub-feature p / D, degree p % D + 1) from features xs
+  // and recurrence rs, into A buffer buf.
+  auto gen = [&](auto pc, Recur<BASIS> (&rs)[2], const float (&xs)[2][G], bf16x8 (&dst)[2]) {
+    constexpr int p = decltype(pc)::value;
+    constexpr int i = p / D;
+    constexpr int j = p % D;
+    if constexpr (j == 0) {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) rs[rb].seed(xs[rb][i], h);
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) dst[rb][p & 7] = (__bf16)rs[rb].cur;
+    if constexpr (j + 1 < D) {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) rs[rb].template advance<j + 1>(xs[rb][i]);
+    }
+  };
+
+  // Every wave runs the same number of iterations (the chunked path has
+  // barriers inside); a wave without a tile of its own in the last round
+  // recomputes the split's last tile and discards the result.
+  for (int tp = tile_begin; tp < tile_end; tp += TS) {
+    const bool active = tp + wg < tile_end;
+    const int tile = active ? tp + wg : tile_end - 1;
+    const int64_t row0 = (int64_t)tile * kTileRows + wq * 64;
+    // Once the last features and the targets of this tile have been read
+    // from the wave's buffer, the buffer takes the copy of the wave's next
+    // tile (two groups and the epilogue ahead of its use for 4+ groups).
+    auto xl_release = [&]() {
+      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the reads returned
+      __asm__ __volatile__("" ::: "memory");
+      if (tile + TS < tile_end) xl_issue(tile + TS);
+    };
+    // Features of the current group (x) and the next one (xn).
+    float x[2][G], xn[2][G];
     if constexpr (XL) {
-      // This tile's copy (issued a tile ago) has landed; the other buffer's
-      // reads all completed in the previous tile, so it takes the next copy.
+      // This tile's copy (issued after the previous tile's last read) has
+      // landed.
       __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
       __asm__ __volatile__("" ::: "memory");
-      if (tile + 1 < tile_end) xl_issue(tile + 1, xbuf ^ 1);
-      xl_read(xbuf, 0, xn);
+      xl_read(0, x);
+      xl_read(n_groups > 1 ? 1 : 0, xn);
+    } else {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int i = 0; i < G; ++i) x[rb][i] = xt[rb][i];
+      load_x(row0, n_groups > 1 ? 1 : 0, xn);
     }
-    // Bias K-step: accumulators start at a_0 - t_k, exactly.
+    // Bias K-step: accumulators start at a_0 - t_k, exactly.  The first
+    // K-step's A values are generated meanwhile.
+    Recur<BASIS> rc[2];
+    [&]<int... P>(std::integer_sequence<int, P...>) {
+      (gen(std::integral_constant<int, P>{}, rc, x, av[0]), ...);
+    }(std::make_integer_sequence<int, 8>{});
     f32x16 acc[2][4];
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
@@ -258,7 +322,7 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
         abias[1] = (__bf16)1.f;
         abias[2] = (__bf16)1.f;
       } else if constexpr (XL) {
-        const float* tl = reinterpret_cast<const float*>(xl_base + xbuf * XB + (N / 4) * 1024);
+        const float* tl = reinterpret_cast<const float*>(xl_base + (N / 4) * 1024);
         split3(-tl[rb * 32 + m], abias);
       } else {
         const int64_t r = row0 + rb * 32 + m;
@@ -268,90 +332,76 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
       for (int cb = 0; cb < 4; ++cb)
         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(abias, bbias[cb], f32x16{}, 0, 0, 0);
     }
+    if constexpr (XL) {
+      if (n_groups <= 2) xl_release();
+    }
 
     for (int chunk = 0; chunk < a.n_chunks; ++chunk) {
       if (a.n_chunks > 1) {
         __syncthreads();
         stage(chunk);
         __syncthreads();
-        load_b(0, bcur);
+        load_b(0, bq[0]);
       }
       const int g_begin = chunk * gpc;
       const int g_end = min(g_begin + gpc, n_groups);
       for (int g = g_begin; g < g_end; ++g) {
-        float x[2][G];
+        if constexpr (!XL) {
+          // The next tile's first features, one group ahead of their use.
+          if (g + 1 == n_groups && tile + TS < tile_end) load_x(row0 + TS * kTileRows, 0, xt);
+        }
+        const int kbase = (g - g_begin) * KS * 32;
+        Recur<BASIS> rcn[2];
+        // K-step k: its eight MFMAs, each pair followed by the B fragment of
+        // K-step k+1 for that column block and two of K-step k+1's A values
+        // (for the last K-step: the next group's first K-step), so the vector
+        // work issues while the matrix core runs.  The scheduling barriers
+        // keep that order.
+        auto kstep = [&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          constexpr int cur = k & 1, nxt = cur ^ 1;
+          int nb = kbase + (k + 1) * 32;
+          nb = nb == chunk_bytes ? 0 : nb;
+          auto pair = [&](auto cc) {
+            constexpr int cb = decltype(cc)::value;
+            acc[0][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[cur][0], bq[cur][cb], acc[0][cb], 0, 0, 0);
+            acc[1][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[cur][1], bq[cur][cb], acc[1][cb], 0, 0, 0);
+            bq[nxt][cb] = *reinterpret_cast<const bf16x8*>(wrow + cb * 32 * RS + nb);
+            if constexpr (k + 1 < KS) {
+              gen(std::integral_constant<int, 8 * (k + 1) + 2 * cb>{}, rc, x, av[nxt]);
+              gen(std::integral_constant<int, 8 * (k + 1) + 2 * cb + 1>{}, rc, x, av[nxt]);
+            } else {
+              gen(std::integral_constant<int, 2 * cb>{}, rcn, xn, av[nxt]);
+              gen(std::integral_constant<int, 2 * cb + 1>{}, rcn, xn, av[nxt]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          };
+          pair(std::integral_constant<int, 0>{});
+          pair(std::integral_constant<int, 1>{});
+          pair(std::integral_constant<int, 2>{});
+          pair(std::integral_constant<int, 3>{});
+        };
+        [&]<int... Ks>(std::integer_sequence<int, Ks...>) {
+          (kstep(std::integral_constant<int, Ks>{}), ...);
+        }(std::make_integer_sequence<int, KS>{});
+        // Advance: the next group's features and recurrence become current.
+        if constexpr (KS % 2 == 1) {
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+          for (int rb = 0; rb < 2; ++rb) av[0][rb] = av[1][rb];
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) bq[0][cb] = bq[1][cb];
+        }
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          rc[rb] = rcn[rb];
 #pragma unroll
           for (int i = 0; i < G; ++i) x[rb][i] = xn[rb][i];
-        if constexpr (XL) {
-          xl_read(xbuf, g + 1 < n_groups ? g + 1 : g, xn);   // no branch in the group body
-        } else {
-          if (g + 1 < n_groups) load_x(row0, g + 1, xn);
-          else if (tile + 1 < tile_end) load_x(row0 + kTileRows, 0, xn);
         }
-
-        const int kbase = (g - g_begin) * KS * 32;
-        bf16x8 av[2][2];
-        Recur<BASIS> rc[2];
-        // Walk the group's G*D values in order; every 8th value completes a
-        // K-step: prefetch the next K-step's B fragments (wrapping to the
-        // chunk's first one at its end), then issue eight MFMAs.  A
-        // fragments alternate between two buffers so the next K-step's
-        // values can be generated while these MFMAs run.
-        auto value = [&](auto pc) {
-          constexpr int p = decltype(pc)::value;
-          constexpr int i = p / D;
-          constexpr int j = p % D;
-          constexpr int ks = p / 8;
-          if constexpr (j == 0) {
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb) rc[rb].seed(x[rb][i], h);
-          }
-#pragma unroll
-          for (int rb = 0; rb < 2; ++rb) av[ks & 1][rb][p & 7] = (__bf16)rc[rb].cur;
-          if constexpr (j + 1 < D) {
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb) rc[rb].template advance<j + 1>(x[rb][i]);
-          }
-          if constexpr ((p & 7) == 7) {
-            int nb = kbase + (ks + 1) * 32;
-            nb = nb == chunk_bytes ? 0 : nb;
-            bf16x8 bnext[4];
-            load_b(nb, bnext);
-#pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-              acc[0][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[ks & 1][0], bcur[cb], acc[0][cb], 0, 0, 0);
-              acc[1][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[ks & 1][1], bcur[cb], acc[1][cb], 0, 0, 0);
-            }
-#pragma unroll
-            for (int cb = 0; cb < 4; ++cb) bcur[cb] = bnext[cb];
-          }
-        };
-        [&]<int... P>(std::integer_sequence<int, P...>) {
-          (value(std::integral_constant<int, P>{}), ...);
-        }(std::make_integer_sequence<int, G * D>{});
-#ifndef GAME_BF16_SCHED
-#define GAME_BF16_SCHED 0
-#endif
-        if constexpr (XL && GAME_BF16_SCHED == 1) {
-          // Interleave: each MFMA followed by a share of the recurrence,
-          // conversion and LDS work of the next K-step.
-#pragma unroll
-          for (int q = 0; q < 8 * KS; ++q) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
-            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);   // VALU
-          }
-        } else if constexpr (XL && GAME_BF16_SCHED == 2) {
-#pragma unroll
-          for (int q = 0; q < 8 * KS; ++q) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
-            if (q % 2 == 0) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-          }
-        } else if constexpr (XL && GAME_BF16_SCHED == 3) {
-          __builtin_amdgcn_iglp_opt(1);
+        if constexpr (XL) {
+          if (g + 2 < n_groups) xl_read(g + 2, xn);
+          if (g + 3 == n_groups) xl_release();
+        } else {
+          load_x(row0, g + 2 < n_groups ? g + 2 : n_groups - 1, xn);
         }
       }
     }
@@ -389,8 +439,9 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
     }
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
-      const float t2 = sum[cb] + s[cb];
-      comp[cb] += fabsf(sum[cb]) >= fabsf(s[cb]) ? (sum[cb] - t2) + s[cb] : (s[cb] - t2) + sum[cb];
+      const float sc = active ? s[cb] : 0.f;
+      const float t2 = sum[cb] + sc;
+      comp[cb] += fabsf(sum[cb]) >= fabsf(sc) ? (sum[cb] - t2) + sc : (sc - t2) + sum[cb];
       sum[cb] = t2;
     }
   }
@@ -410,7 +461,9 @@ __global__ __launch_bounds__(kFitThreads, 1) void fitness_bf16_kernel(FitArgs a)
   __syncthreads();
   if (threadIdx.x < kCols) {
     const int c = threadIdx.x;
-    const double v = ((red[c] + red[kCols + c]) + red[2 * kCols + c]) + red[3 * kCols + c];
+    double v = red[c];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += red[w * kCols + c];
     a.partial[(int64_t)split * a.ld_partial + c0 + c] = v;
   }
 }
@@ -419,8 +472,8 @@ size_t fitness_bf16_lds_bytes(const FitArgs& a, int degree, bool xl) {
   const int G = group_size(degree);
   const int KS = G * degree / 8;
   const size_t w = (size_t)128 * bf16_row_bytes(a.pairs_per_chunk * KS) +
-                   (xl ? (size_t)4 * 2 * xl_buffer_bytes(a.N) : 0);
-  const size_t red = 4 * 128 * sizeof(double);
+                   (xl ? (size_t)bf16_waves(degree) * xl_buffer_bytes(a.N) : 0);
+  const size_t red = (size_t)bf16_waves(degree) * 128 * sizeof(double);
   return w > red ? w : red;
 }
 
@@ -466,7 +519,8 @@ static hipError_t launch_variant(const FitArgs& a, hipStream_t s) {
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((fitness_bf16_kernel<BASIS, D, XL>), dim3(grid), dim3(kFitThreads), lds, s, a);
+  hipLaunchKernelGGL((fitness_bf16_kernel<BASIS, D, XL>), dim3(grid), dim3(64 * bf16_waves(D)), lds, s,
+                     a);
   return hipGetLastError();
 }
 
