@@ -357,10 +357,12 @@ int game_batch_destroy(game_batch_t b);
 int game_batch_tune(game_batch_t b, int32_t tiles_per_item, int32_t grid);
 
 /* The batch autotuner: times the batch's fitness launch (HIP events, reps
- * launches each) for every tiles_per_item in {1,2,4,8,16,32} and grid in
- * {256,512,1024}, keeps the fastest and reports it; times_ms (may be NULL)
- * receives the 18 averages in that order.  Leaves the populations as they
- * were.  Synchronises the stream. */
+ * launches each) for every tiles_per_item in {1,2,4,8,16,32,64,128} and grid
+ * in {256,512,1024}, keeps the fastest and reports it; times_ms (may be
+ * NULL) receives the GAME_AUTOTUNE_CANDIDATES averages in that order (tiles
+ * outer, grid inner).  Leaves the populations as they were.  Synchronises
+ * the stream. */
+#define GAME_AUTOTUNE_CANDIDATES 24
 int game_batch_autotune(game_batch_t b, int32_t reps, int32_t* tiles_per_item, int32_t* grid,
                         float* best_ms, float* times_ms);
 

@@ -1361,7 +1361,7 @@ int game_batch_autotune(game_batch_t b, int32_t reps, int32_t* best_tiles, int32
                         float* best_ms, float* times_ms) {
   if (!b) return fail(GAME_EINVAL, "batch is NULL");
   if (reps < 1) return fail(GAME_EINVAL, "reps < 1");
-  static const int kTiles[] = {1, 2, 4, 8, 16, 32};
+  static const int kTiles[] = {1, 2, 4, 8, 16, 32, 64, 128};
   static const int kGrids[] = {256, 512, 1024};
   hipEvent_t e0, e1;
   GAME_HIP(hipEventCreate(&e0));

@@ -404,7 +404,7 @@ class Game:
 
 
 # ------------------------------------------------------------------ batches
-AUTOTUNE_TILES = (1, 2, 4, 8, 16, 32)
+AUTOTUNE_TILES = (1, 2, 4, 8, 16, 32, 64, 128)
 AUTOTUNE_GRIDS = (256, 512, 1024)
 
 

@@ -163,3 +163,9 @@ def test_predict_null_handle_fails_without_gpu():
     assert L.game_predict(None, None, 0, None, 1, None) == game.GAME_EINVAL
     assert L.game_classify(None, None, None, 0, None, 1, ctypes.c_float(0.5), None) == game.GAME_EINVAL
     assert L.game_merit(None, None) == game.GAME_EINVAL
+
+
+def test_autotune_candidate_count_matches_header():
+    src = open(HEADER).read()
+    n = int(re.search(r"#define\s+GAME_AUTOTUNE_CANDIDATES\s+(\d+)", src).group(1))
+    assert n == len(game.AUTOTUNE_TILES) * len(game.AUTOTUNE_GRIDS)

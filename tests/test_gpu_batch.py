@@ -102,7 +102,8 @@ def test_autotune_leaves_populations_and_picks_a_candidate(gg):
     before = [bits(b.population(r)[0].cpu().numpy()) for r in range(b.n_runs)]
     res = b.autotune(reps=2)
     assert res["tiles_per_item"] in gg.AUTOTUNE_TILES and res["grid"] in gg.AUTOTUNE_GRIDS
-    assert len(res["times_ms"]) == 18 and all(v > 0 for v in res["times_ms"].values())
+    assert len(res["times_ms"]) == len(gg.AUTOTUNE_TILES) * len(gg.AUTOTUNE_GRIDS)
+    assert all(v > 0 for v in res["times_ms"].values())
     assert abs(res["ms"] - min(res["times_ms"].values())) < 1e-6
     after = [bits(b.population(r)[0].cpu().numpy()) for r in range(b.n_runs)]
     assert all(np.array_equal(x, y) for x, y in zip(before, after))
