@@ -342,6 +342,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the BF16, batched and surrogate workloads")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the paper-shaped scaling table (shared-gene polytrigo runs)")
     ap.add_argument("--no-target", action="store_true",
                     help="skip the time-to-target comparison (plain FP32 vs surrogate + BF16)")
     ap.add_argument("--target-generations", type=int, default=300,
@@ -431,8 +433,9 @@ def main():
         log("batched form: building inputs, autotuning, timing")
         forms["batched"] = form_batched(gg, max(5, args.steps // 5), max(2, args.warmup // 5))
         out["forms"] = forms
-        log("paper-shaped scaling table: shared-gene polytrigo, 16 runs")
-        out["paper_shaped"] = form_paper_shaped(gg)
+        if not args.no_paper:
+            log("paper-shaped scaling table: shared-gene polytrigo, 16 runs")
+            out["paper_shaped"] = form_paper_shaped(gg)
         if not args.no_target:
             log("time to target: plain FP32, plain BF16, surrogate + BF16")
             out["time_to_target"] = form_time_to_target(gg, pprob, args.target_generations)
