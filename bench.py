@@ -223,8 +223,8 @@ def form_time_to_target(gg, prob, plain_generations=300, cap=3):
     target = plain["train_mse_fp64"]
     plain["reached"] = True
     bf16 = _run_to_target(gg, prob, gg.GAME_BF16, cap * plain_generations, target)
-    sur_cfg = dict(hidden=256, fp32_operands=0, archive=16384, minibatch=1024, train_steps=32,
-                   lr=1e-2, oversample=8, audit=64, rho_min=0.8, min_archive=4096, seed=0)
+    sur_cfg = dict(hidden=256, fp32_operands=0, archive=16384, minibatch=1024, train_steps=24,
+                   lr=1.5e-2, oversample=8, audit=64, rho_min=0.8, min_archive=4096, seed=0)
     chosen = _run_to_target(gg, prob, gg.GAME_BF16, cap * plain_generations, target, sur_cfg)
     return {"workload": "precision problem (1,000,000 x 32, Chebyshev degree 8, population "
                         "4,096, validation 250,000 patterns), seed 0; target = plain FP32 best "

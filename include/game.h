@@ -265,8 +265,8 @@ typedef struct {
   int32_t fp32_operands;  /* 0: BF16 operands, FP32 accumulation; 1: FP32      */
   int32_t archive;        /* archive capacity in chromosomes (16384)          */
   int32_t minibatch;      /* rows per Adam step (1024)                        */
-  int32_t train_steps;    /* Adam steps per generation (32)                   */
-  float lr;               /* Adam learning rate (1e-2)                        */
+  int32_t train_steps;    /* Adam steps per generation (24)                   */
+  float lr;               /* Adam learning rate (1.5e-2)                      */
   int32_t oversample;     /* children generated per kept child (8)            */
   int32_t audit;          /* children scored exactly per generation (64)      */
   float rho_min;          /* rank correlation needed to screen (0.8)          */

@@ -894,13 +894,14 @@ int game_surrogate_config_default(game_surrogate_config* c) {
   memset(c, 0, sizeof *c);
   c->hidden = 256;
   c->fp32_operands = 0;
-  // Tuned on the 1M x 32, degree-8 precision problem (population 4,096):
-  // a window of the last four generations, 32 steps at 1e-2 per generation
-  // reach rank correlations of 0.8-0.9 after ~100 generations.
+  // Tuned on the 1M x 32, degree-8 problem with population 4,096 for the
+  // time to reach a target error: a window of the last four generations and
+  // 24 Adam steps at 1.5e-2 per generation (rank correlations 0.8-0.9 after
+  // ~40 generations; more steps screen more generations but cost more).
   c->archive = 16384;
   c->minibatch = 1024;
-  c->train_steps = 32;
-  c->lr = 1e-2f;
+  c->train_steps = 24;
+  c->lr = 1.5e-2f;
   c->oversample = 8;
   c->audit = 64;
   c->rho_min = 0.8f;
