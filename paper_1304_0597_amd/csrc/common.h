@@ -48,8 +48,12 @@ inline int max_splits(int ld_partial) {
 constexpr int kTileRows = 256;
 constexpr int kTileCols = 64;
 constexpr int kFitThreads = 256;
-// Largest K-chunk kept in LDS at once, in MFMA K-steps per lane half.
+// Largest K kept in LDS at once, in MFMA K-steps per lane half: a
+// chromosome tile whose genes fit is staged once; otherwise its genes pass
+// through two LDS buffers in chunks of at most kChunkSteps K-steps, the next
+// chunk's copy in flight while the current one is used.
 constexpr int kMaxChunkSteps = 128;
+constexpr int kChunkSteps = 64;
 
 // Device-side state of a run.  Only the rank kernel writes gen/stop/best.
 struct RunState {

@@ -13,9 +13,12 @@
 //    recurrence, one value per K-step.  K is ordered so that the two lane
 //    halves of a K-step carry sub-features 2q and 2q+1 at the same degree j,
 //    so a lane's recurrence never crosses a feature boundary.
-//  * The B operand (K x chromosomes) is staged once per workgroup in LDS in
-//    that permuted order (odd row stride: conflict-free ds_read_b32).  When
-//    K does not fit, it is staged in chunks of whole feature pairs.
+//  * The B operand (K x chromosomes) is copied once per workgroup into LDS,
+//    one row per chromosome in the canonical gene order (odd row stride:
+//    conflict-free ds_read_b32), by LDS DMA (global_load_lds_dword), so the
+//    copy costs no registers and one memory round trip.  When K does not
+//    fit, it passes through two buffers in chunks of whole feature pairs,
+//    the next chunk's copy in flight while the current one is used.
 //  * Accumulators start at zero; the epilogue adds the bias a_0(p), takes
 //    the residual against t_k, squares it (or applies the error function)
 //    and sums the lane's 32 rows in float32, then adds into a float64
@@ -83,7 +86,8 @@ hipError_t launch_fitness_f32(const FitArgs& a, int basis, int degree, hipStream
 }
 
 size_t fitness_lds_bytes(const FitArgs& a, int degree) {
-  const size_t w = (size_t)kTileCols * (2 * a.pairs_per_chunk * degree + 1) * sizeof(float);
+  const size_t w = (size_t)(a.n_chunks > 1 ? 2 : 1) * kTileCols *
+                   (2 * a.pairs_per_chunk * degree + 1) * sizeof(float);
   const size_t red = 4 * 64 * sizeof(double);
   return w > red ? w : red;
 }
@@ -91,9 +95,8 @@ size_t fitness_lds_bytes(const FitArgs& a, int degree) {
 void plan_fitness(FitArgs& a, int degree, int basis) {
   a.U = (basis == 3 ? 2 : 1) * a.N;
   a.Q = (a.U + 1) / 2;
-  int ppc = kMaxChunkSteps / degree;
+  int ppc = a.Q * degree <= kMaxChunkSteps ? a.Q : kChunkSteps / degree;
   if (ppc < 1) ppc = 1;
-  if (ppc > a.Q) ppc = a.Q;
   a.pairs_per_chunk = ppc;
   a.n_chunks = (a.Q + ppc - 1) / ppc;
   a.n_ctiles = (a.n_chrom + kTileCols - 1) / kTileCols;

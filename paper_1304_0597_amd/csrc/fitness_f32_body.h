@@ -22,12 +22,56 @@ __device__ __forceinline__ float error_term(float v, float R) {
   return e;
 }
 
+// Wave-uniform copies (readfirstlane) of launch parameters.
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ int64_t uniform(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T* uniform(T* p) {
+  return reinterpret_cast<T*>(uniform((int64_t)reinterpret_cast<uintptr_t>(p)));
+}
+
+// A pointer to global memory as such: its loads are global_load rather than
+// flat_load, whose completion an LDS wait would also have to cover.
+typedef const float __attribute__((address_space(1)))* gptr_f32;
+__device__ __forceinline__ gptr_f32 global_f32(const float* p) { return (gptr_f32)p; }
+
 // Tile range [split's tiles] x chromosome tile ctile of the launch described
-// by a; writes a.partial[split * ld_partial + chromosome].  genes: the
+// by a_in; writes a.partial[split * ld_partial + chromosome].  genes: the
 // chromosomes being scored; lds: the workgroup's dynamic LDS.
 template <int BASIS, int D>
-__device__ __forceinline__ void fitness_f32_block(const FitArgs& a, const float* __restrict__ genes,
+__device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const float* __restrict__ genes,
                                                   int split, int ctile, float* lds) {
+  // The parameters the body uses, read once into scalar registers.  (In the
+  // batched kernel a_in sits in private memory behind a generic pointer that
+  // any store might alias; left there, the loops would reload it.)
+  FitArgs a;
+  a.X = uniform(a_in.X);
+  a.t = uniform(a_in.t);
+  a.partial = uniform(a_in.partial);
+  a.NP = uniform(a_in.NP);
+  a.N = uniform(a_in.N);
+  a.K = uniform(a_in.K);
+  a.n_chrom = uniform(a_in.n_chrom);
+  a.U = uniform(a_in.U);
+  a.Q = uniform(a_in.Q);
+  a.pairs_per_chunk = uniform(a_in.pairs_per_chunk);
+  a.n_chunks = uniform(a_in.n_chunks);
+  a.ld_partial = uniform(a_in.ld_partial);
+  a.tiles_per_split = uniform(a_in.tiles_per_split);
+  a.n_tiles = uniform(a_in.n_tiles);
+  a.error_fn = uniform(a_in.error_fn);
+  a.R = uniform(a_in.R);
+  genes = uniform(genes);
+  split = uniform(split);
+  ctile = uniform(ctile);
+  lds = uniform(lds);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int m = lane & 31;
@@ -37,35 +81,50 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a, const float*
   const int ppc = a.pairs_per_chunk;
   const int SC = ppc * D;          // K-steps per chunk
   const int WS = 2 * SC + 1;       // LDS row stride in floats (odd)
+  const int BUF = kTileCols * WS;  // floats per gene buffer
+  const int nk = (2 * SC + 63) >> 6;  // 64-gene pieces of a row
   const int K = a.K;
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
 
   float w0[2];
 #pragma unroll
   for (int cb = 0; cb < 2; ++cb) {
     const int n = c0 + cb * 32 + m;
-    w0[cb] = n < a.n_chrom ? genes[(int64_t)n * K] : 0.f;
+    w0[cb] = n < a.n_chrom ? global_f32(genes)[(int64_t)n * K] : 0.f;
   }
 
-  // Stage the genes of feature pairs [chunk*ppc, chunk*ppc + ppc) of this
-  // chromosome tile: lds[c*WS + half*SC + qq*D + (j-1)].
-  auto stage = [&](int chunk) {
-    const int g0 = chunk * ppc * 2 * D;       // first expansion gene of the chunk
-    const int span = 2 * SC;
-    for (int idx = threadIdx.x; idx < kTileCols * span; idx += kFitThreads) {
-      const int c = idx / span;
-      const int g = idx - c * span;           // offset within the chunk
-      const int u_off = g / D;
-      const int j = g - u_off * D;
-      const int u = chunk * ppc * 2 + u_off;
-      const int n = c0 + c;
-      float v = 0.f;
-      if (n < a.n_chrom && u < a.U) v = genes[(int64_t)n * K + 1 + g0 + g];
-      lds[c * WS + (u_off & 1) * SC + (u_off >> 1) * D + j] = v;
+  // Issue the copy of the chunk's genes (sub-features [u0, u0 + 2 ppc)) into
+  // buffer buf: row c = genes 1 + u0*D ... of chromosome c0 + c, canonical
+  // order.  Rows past the population repeat the last chromosome (their sums
+  // are never read).  Gene slots of a sub-feature past U (the odd half of the
+  // last pair) are zeroed: that lane's expansion of x = 0 is not zero.  The
+  // copy has landed once this wave's vmcnt reaches zero.
+  auto stage_issue = [&](int chunk, int buf) {
+    const int u0 = chunk * ppc * 2;
+    const int rem = a.U - u0;
+    const int valid = min(2 * SC, rem * D);
+    float* dst0 = lds + buf * BUF;
+    const float* src0 = genes + 1 + u0 * D + lane;
+    for (int i = wave_u; i < kTileCols * nk; i += kFitThreads / 64) {
+      const int c = i / nk;
+      const int k = i - c * nk;
+      const int n = min(c0 + c, a.n_chrom - 1);
+      if (k * 64 + lane < valid)
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(src0 + (int64_t)n * K + k * 64),
+            (__attribute__((address_space(3))) void*)(dst0 + c * WS + k * 64), 4, 0, 0);
+    }
+    if ((rem & 1) && rem < 2 * ppc) {
+      for (int idx = threadIdx.x; idx < kTileCols * D; idx += kFitThreads) {
+        const int c = idx / D;
+        dst0[c * WS + rem * D + (idx - c * D)] = 0.f;
+      }
     }
   };
 
   if (a.n_chunks == 1) {
-    stage(0);
+    stage_issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's copies landed
     __syncthreads();
   }
 
@@ -83,18 +142,22 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a, const float*
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
       const int64_t r = row0 + rb * 32 + m;
-      xo[rb] = (r < NP && fvalid) ? a.X[r * N + f] : 0.f;
+      xo[rb] = (r < NP && fvalid) ? global_f32(a.X)[r * N + f] : 0.f;
     }
   };
 
   float xn[2] = {0.f, 0.f};
   if (tile_begin < tile_end) load_x((int64_t)tile_begin * kTileRows + wave * 64, 0, xn);
+  // Chunked genes: stage index st runs over (tile, chunk) in loop order and
+  // uses buffer st & 1.
+  int st = 0;
+  if (a.n_chunks > 1 && tile_begin < tile_end) stage_issue(0, 0);
 
   for (int tile = tile_begin; tile < tile_end; ++tile) {
     const int64_t row0 = (int64_t)tile * kTileRows + wave * 64;
     // One target per lane (the wave's 64 rows); the epilogue redistributes
     // them across lanes, so the load's latency hides behind the K loop.
-    const float t_lane = a.t[row0 + lane < NP ? row0 + lane : NP - 1];
+    const float t_lane = global_f32(a.t)[row0 + lane < NP ? row0 + lane : NP - 1];
     // Accumulators start at zero (an inline constant, nothing to keep live
     // across tiles); the bias joins in the epilogue.
     f32x16 acc[2][2];
@@ -104,10 +167,16 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a, const float*
     acc[1][1] = f32x16{};
 
     for (int chunk = 0; chunk < a.n_chunks; ++chunk) {
+      const float* wbuf = lds;
       if (a.n_chunks > 1) {
+        // Every wave's copy of this chunk has landed and every wave is done
+        // with the other buffer: start the copy of the next stage into it.
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
         __syncthreads();
-        stage(chunk);
-        __syncthreads();
+        if (chunk + 1 < a.n_chunks) stage_issue(chunk + 1, (st + 1) & 1);
+        else if (tile + 1 < tile_end) stage_issue(0, (st + 1) & 1);
+        wbuf = lds + (st & 1) * BUF;
+        ++st;
       }
       const int q_begin = chunk * ppc;
       const int q_end = min(q_begin + ppc, a.Q);
@@ -119,7 +188,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a, const float*
         Recur<BASIS> rc[2];
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) rc[rb].seed(x[rb], h);
-        const float* wl = lds + m * WS + h * SC + (q - q_begin) * D;
+        const float* wl = wbuf + m * WS + (2 * (q - q_begin) + h) * D;
         // One K-step per degree: two MFMA columns x two row blocks, then the
         // recurrence moves every lane's A value to the next degree.
         auto kstep = [&](auto jc) {

@@ -123,6 +123,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1304_0597_amd.build`")
+        # torch first: libgame then binds to the HIP runtime torch has loaded
+        # (two HIP runtimes in one process do not share devices or streams).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)

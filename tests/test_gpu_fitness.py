@@ -61,6 +61,9 @@ SHAPES = [
     (513, 64, 2, 100), (300, 33, 10, 70), (1100, 300, 1, 66),
     # few chromosomes over many patterns: hundreds of pattern splits
     (300001, 4, 2, 10),
+    # K-chunks through the two gene buffers over several tiles per split,
+    # odd sub-feature count (zeroed half pair in the last chunk)
+    (8000, 33, 10, 1100),
 ]
 
 
