@@ -323,8 +323,9 @@ int game_surrogate_stats(game_surrogate_t s, float* rho, int32_t* screened_last,
 /* ------------------------------------------------------------------------
  * Batches: many independent runs of uneven sizes advanced together.  Each
  * generation is one persistent fitness launch over a work list of (run,
- * 64-chromosome tile, pattern split) items drained through an atomic queue,
- * one rank/stop-test launch and one genetic-step launch for all runs;
+ * 64-chromosome tile, pattern split) items drained through atomic queues
+ * (one per XCD; the tiles of one split share a queue, hence one L2), one
+ * rank/stop-test launch and one genetic-step launch for all runs;
  * game_batch_run replays a captured HIP graph of such generations.  Every
  * run follows exactly the trajectory it would follow alone (same draws,
  * same fixed-order sums).  FP32 precision only.

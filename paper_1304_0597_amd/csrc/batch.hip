@@ -2,14 +2,19 @@
 // in one persistent launch.
 //
 // The work of a generation is a list of items (run, 64-chromosome tile,
-// pattern split), ordered by decreasing cost on the host.  A fixed grid of
-// workgroups drains the list through an atomic queue head; each item is the
-// float32 fitness computation of that run's tile over that split (the
-// single-run float32 body itself, dispatched on the run's basis and degree),
-// and writes its float64 partial sums to the run's own partial array.  Which workgroup takes which
-// item does not affect any result: every item owns its output slots and the
-// per-run finish sums them in a fixed order.  Every workgroup leaves the
-// loop once the queue head passes the last item.
+// pattern split).  The host groups the items of one (run, split) - every
+// chromosome tile over the same patterns - and deals the groups, largest
+// first, to the queue with the least work, one queue per XCD.  A fixed grid
+// of workgroups drains the queues through atomic heads: workgroup b serves
+// the queue of its own XCD (b % 8) first, so the chromosome tiles of a split
+// run side by side on one XCD and read its patterns through one L2, then
+// takes what is left in the other queues.  Each item is the float32 fitness
+// computation of that run's tile over that split (the single-run float32
+// body itself, dispatched on the run's basis and degree) and writes its
+// float64 partial sums to the run's own partial array.  Which workgroup
+// takes which item does not affect any result: every item owns its output
+// slots and the per-run finish sums them in a fixed order.  A workgroup
+// leaves the loop once every queue head has passed its queue's end.
 #include "fitness_f32_body.h"
 
 namespace game {
@@ -41,12 +46,26 @@ __device__ void item_degree(int degree, const FitArgs& fa, const float* genes, i
 __global__ __launch_bounds__(kFitThreads, 2) void fitness_batch_kernel(BatchArgs a) {
   extern __shared__ float lds[];
   __shared__ int item_sh;
+  const int home = blockIdx.x % kXcds;
+  int tried = 0;  // queues found empty so far (thread 0 only); heads only grow
   for (;;) {
     __syncthreads();  // the previous item is done with item_sh and LDS
-    if (threadIdx.x == 0) item_sh = atomicAdd(a.counter, 1);
+    if (threadIdx.x == 0) {
+      int got = -1;
+      while (tried < kXcds) {
+        const int q = (home + tried) % kXcds;
+        const int i = a.queue_begin[q] + atomicAdd(&a.counter[q], 1);
+        if (i < a.queue_begin[q + 1]) {
+          got = i;
+          break;
+        }
+        ++tried;
+      }
+      item_sh = got;
+    }
     __syncthreads();
     const int it = item_sh;
-    if (it >= a.n_items) break;
+    if (it < 0) break;
     const BatchItem w = a.items[it];
     const BatchRun& run = a.runs[w.run];
     const int stopped = run.state->stop;

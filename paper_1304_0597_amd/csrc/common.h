@@ -249,10 +249,15 @@ struct BatchItem {
   int32_t cost;             // relative work, for ordering
 };
 
+// The batched fitness work list is split into one queue per XCD (8 on
+// MI355X); workgroup b starts on queue b % 8, the XCD the hardware dispatches
+// it to, and takes work from the other queues once its own is empty.
+constexpr int kXcds = 8;
+
 struct BatchArgs {
   const BatchRun* runs;
   const BatchItem* items;
-  int32_t* counter;         // work-queue head of the fitness launch
+  int32_t* counter;         // kXcds queue heads of the fitness launch
   const int32_t* rank_block_run;
   const int32_t* ga_wave_run;
   int32_t n_runs;
@@ -261,6 +266,7 @@ struct BatchArgs {
   int32_t n_ga_waves;
   int32_t max_population;
   int32_t grid;             // persistent fitness workgroups
+  int32_t queue_begin[kXcds + 1];  // queue q holds items [queue_begin[q], queue_begin[q+1])
 };
 hipError_t launch_fitness_batch(const BatchArgs& a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_finish_rank_batch(const BatchArgs& a, hipStream_t s);

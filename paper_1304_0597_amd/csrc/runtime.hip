@@ -1094,6 +1094,7 @@ struct game_batch_ctx {
   int32_t max_pop;
   int32_t grid;
   int32_t tiles_per_item;
+  int32_t queue_begin[kXcds + 1];
   int32_t max_gen;
   size_t lds;
   hipStream_t stream;
@@ -1142,7 +1143,7 @@ BatchLayout batch_layout(const game_run_desc* runs, int32_t n) {
   size_t off = 0;
   L.runs = off; off += align_up(sizeof(BatchRun) * n);
   L.items = off; off += align_up(sizeof(BatchItem) * cap);
-  L.counter = off; off += align_up(sizeof(int32_t));
+  L.counter = off; off += align_up(sizeof(int32_t) * kXcds);
   L.rank_map = off; off += align_up(sizeof(int32_t) * rb);
   L.ga_map = off; off += align_up(sizeof(int32_t) * gw);
   L.states = off; off += align_up(sizeof(RunState) * n);
@@ -1166,7 +1167,13 @@ BatchLayout batch_layout(const game_run_desc* runs, int32_t n) {
 // `tiles` 256-row tiles; items are (run, chromosome tile, split), heaviest
 // first so the queue ends with small items.
 int build_items(game_batch_ctx* b, int32_t tiles) {
-  std::vector<BatchItem> items;
+  // Groups: every chromosome tile of one (run, split), which read the same
+  // patterns.  Dealt largest first to the least-loaded of the kXcds queues.
+  struct Group {
+    int32_t run, split;
+    int64_t cost;
+  };
+  std::vector<Group> groups;
   for (int r = 0; r < b->n_runs; ++r) {
     BatchRun& run = b->runs[r];
     int splits = (run.n_tiles + tiles - 1) / tiles;
@@ -1174,14 +1181,32 @@ int build_items(game_batch_ctx* b, int32_t tiles) {
     if (splits < 1) splits = 1;
     run.tiles_per_split = (run.n_tiles + splits - 1) / splits;
     run.n_splits = (run.n_tiles + run.tiles_per_split - 1) / run.tiles_per_split;
-    for (int c = 0; c < run.n_ctiles; ++c)
-      for (int sp = 0; sp < run.n_splits; ++sp) {
-        const int rows = std::min(run.tiles_per_split, run.n_tiles - sp * run.tiles_per_split);
-        items.push_back({r, c, sp, rows * run.Q * run.D});
-      }
+    for (int sp = 0; sp < run.n_splits; ++sp) {
+      const int64_t rows = std::min(run.tiles_per_split, run.n_tiles - sp * run.tiles_per_split);
+      groups.push_back({r, sp, rows * run.Q * run.D * run.n_ctiles});
+    }
   }
-  std::stable_sort(items.begin(), items.end(),
-                   [](const BatchItem& x, const BatchItem& y) { return x.cost > y.cost; });
+  std::stable_sort(groups.begin(), groups.end(),
+                   [](const Group& x, const Group& y) { return x.cost > y.cost; });
+  std::vector<std::vector<int32_t>> dealt(kXcds);
+  int64_t load[kXcds] = {};
+  for (int32_t g = 0; g < (int32_t)groups.size(); ++g) {
+    const int q = (int)(std::min_element(load, load + kXcds) - load);
+    dealt[q].push_back(g);
+    load[q] += groups[g].cost;
+  }
+  std::vector<BatchItem> items;
+  for (int q = 0; q < kXcds; ++q) {
+    b->queue_begin[q] = (int32_t)items.size();
+    for (const int32_t g : dealt[q]) {
+      const BatchRun& run = b->runs[groups[g].run];
+      const int rows = std::min(run.tiles_per_split,
+                                run.n_tiles - groups[g].split * run.tiles_per_split);
+      for (int c = 0; c < run.n_ctiles; ++c)
+        items.push_back({groups[g].run, c, groups[g].split, rows * run.Q * run.D});
+    }
+  }
+  b->queue_begin[kXcds] = (int32_t)items.size();
   if ((int64_t)items.size() > b->item_capacity) return fail(GAME_EINVAL, "too many items");
   GAME_HIP(hipMemcpyAsync(b->items_dev, items.data(), sizeof(BatchItem) * items.size(),
                           hipMemcpyHostToDevice, b->stream));
@@ -1210,6 +1235,7 @@ BatchArgs batch_args(const game_batch_ctx* b) {
   a.n_ga_waves = b->n_ga_waves;
   a.max_population = b->max_pop;
   a.grid = b->grid;
+  for (int q = 0; q <= kXcds; ++q) a.queue_begin[q] = b->queue_begin[q];
   return a;
 }
 
