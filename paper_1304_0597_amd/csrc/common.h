@@ -287,14 +287,22 @@ struct GemmArgs {
   int32_t M, N, K;
   int32_t act;              // 0 none, 1 GELU, 2 times GELU'(aux)
   const int32_t* skip;      // when set and nonzero the launch does nothing
-  float* rowsum;            // when set: rowsum[m] = sum_k A(m, k) in float32
-  int32_t k_split;          // > 1: K cut into k_split ranges summed in a fixed order
-  float* part;              // k_split > 1: [k_split][M][N] partial products
-  float* part_rs;           // k_split > 1 with rowsum: [k_split][M] partial row sums
+  // Split products (weight gradients over a minibatch).  When part is set,
+  // K is cut into k_split ranges of whole 16-value steps and range z writes
+  // its raw sum to part[z * part_ld + m * ldc + n] (no bias, no epilogue);
+  // with rowsum_part set it also writes sum_k A(m, k) over its range to
+  // rowsum_part[z * part_ld + m].  Readers add the ranges in order z = 0, 1, ...
+  float* part;
+  float* rowsum_part;
+  int64_t part_ld;
+  int32_t k_split;
 };
-// Number of K ranges for a product whose K (a minibatch) is long and whose
-// M x N is small: 128 or more K values per range, at most 8 ranges.
-inline int gemm_k_split(int K) { return K >= 256 ? (K / 128 < 8 ? K / 128 : 8) : 1; }
+// Ranges for a split product of length K: at most 512 K values each (one
+// load round per wave of the small-product kernel), at most 8 ranges.
+inline int gemm_k_split(int K) {
+  const int r = (K + 511) / 512;
+  return r < 1 ? 1 : (r > 8 ? 8 : r);
+}
 hipError_t launch_gemm(const GemmArgs& g, bool bf16, hipStream_t s);
 // Output layer (and with t set, its backward); see out_layer_kernel.
 hipError_t launch_out_layer(const float* H2, const float* w3, const float* b3, int B, int H,
@@ -313,8 +321,12 @@ struct SurrogateState {
   int32_t skip;             // 1 when the candidates need no full scoring (stopped or not used)
   int32_t pad[7];
 };
-hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
-                       SurrogateState* st, const int32_t* skip, hipStream_t s);
+// Adam on n parameters whose gradient is the sum of ks ranges
+// part[z * n + i], added in order z = 0, 1, ...
+hipError_t launch_adam(float* p, const float* part, int ks, float* m, float* v, int64_t n,
+                       float lr, SurrogateState* st, const int32_t* skip, hipStream_t s);
+// g[i] = sum over z < ks of part[z * n + i], in order.
+hipError_t launch_sum_ranges(float* g, const float* part, int ks, int64_t n, hipStream_t s);
 
 // Surrogate kernels built with the Philox draws (stream 3).
 hipError_t launch_mlp_init(float* params, int n_in, int hidden, uint64_t seed, hipStream_t s);

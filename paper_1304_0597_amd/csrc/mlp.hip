@@ -1,22 +1,26 @@
 // Fitness-surrogate network kernels: a multilayer perceptron with GELU
 // hidden layers (genes -> standardised log error), trained on the GPU.
 //
-// gemm_kernel computes C[m][n] = sum_k A(m,k) B(n,k) with arbitrary element
-// strides for A and B (so forward products, weight gradients dZ^T X and
-// input gradients dZ W all use one kernel), on MFMA: BF16 operands with FP32
+// Products C[m][n] = sum_k A(m,k) B(n,k) with arbitrary element strides for
+// A and B (so forward products, weight gradients dZ^T X and input gradients
+// dZ W all use one argument block), on MFMA: BF16 operands with FP32
 // accumulation (v_mfma_f32_32x32x16_bf16), or FP32 operands
 // (v_mfma_f32_32x32x2_f32) for a full-precision mode.  Epilogues: + bias[n],
 // then identity, GELU (optionally storing the pre-activation), or
 // multiplication by GELU'(aux[m][n]) (the backward of a GELU layer).
-// A workgroup of 4 waves computes a 64x64 tile of C from 64x32 slices of A
-// and B staged in LDS; out-of-range rows, columns and k read as zero.  Each
-// operand is staged with consecutive threads along its unit-stride index,
-// so the global reads are coalesced whichever way the operand is laid out.
-// Optionally the workgroups of the first column tile also sum the rows of
-// A over k (the bias gradient of a layer comes with its weight gradient).
-// Long-K products with a small M x N (weight gradients over a minibatch)
-// split K over blockIdx.z; the ranges' partial results are added in a fixed
-// order by gemm_reduce_kernel, so results do not depend on scheduling.
+//
+// Two kernels serve them.  Minibatch-sized products (M <= 4096 rows, and
+// every split product) are latency-bound: gemm_small_kernel gives each
+// workgroup a 32x32 tile of C and cuts K across its 8 waves; each wave
+// loads its operand values straight from global memory into registers (all
+// loads of a round in flight at once), runs its MFMAs, and the 8 partial
+// tiles are added in a fixed order through LDS.  Weight gradients (K = the
+// minibatch) also split K over blockIdx.z into ranges whose raw sums the
+// Adam launch adds in order, and the bias gradient (the row sum of the
+// product's A operand) comes from the same registers.  Larger products (the
+// forward pass over all oversampled candidates) use gemm_kernel: 64x64
+// tiles from 64x128 slices of A and B staged in LDS.  Out-of-range rows,
+// columns and k read as zero in both.  Results never depend on scheduling.
 #include <math.h>
 
 #include "common.h"
@@ -93,6 +97,31 @@ __device__ __forceinline__ void stage_slice(float* S, const float* X, int64_t ld
   }
 }
 
+// The arithmetic of a product, whichever kernel runs it: K is cut into
+// 16-value steps, the steps into kSmallWaves ranges of ceil(steps /
+// kSmallWaves); each range is accumulated from zero by MFMAs in step order
+// (a bf16 step is one 32x32x16 MFMA over k = 16 s + 8 h + v; an FP32 step is
+// eight 32x32x2 MFMAs, MFMA v pairing k = 16 s + v and 16 s + 8 + v), and
+// the range sums are added in range order.  So a row's output does not
+// depend on how many rows the product has (the network's predictions for a
+// chromosome are the same in any batch).
+constexpr int kSmallWaves = 8;
+constexpr int kSmallSteps = 4;
+constexpr int kSmallMaxM = 4096;
+
+// Epilogue of output (m, n) with the product value z.
+__device__ __forceinline__ void gemm_store(const GemmArgs& g, int m, int n, float z) {
+  if (g.bias) z += g.bias[n];
+  const int64_t off = (int64_t)m * g.ldc + n;
+  if (g.act == 1) {
+    if (g.Z) g.Z[off] = z;
+    z = gelu_f(z);
+  } else if (g.act == 2) {
+    z *= gelu_grad_f(g.aux[(int64_t)m * g.ld_aux + n]);
+  }
+  g.C[off] = z;
+}
+
 template <bool BF16>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   extern __shared__ float gemm_lds[];
@@ -104,27 +133,26 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   const int wm = wave >> 1, wn = wave & 1;       // 2 x 2 waves of 32 x 32
   const int m0 = blockIdx.y * kGemmTile, n0 = blockIdx.x * kGemmTile;
   const int l32 = lane & 31, h = lane >> 5;
-  // K range of this split (whole 32-value steps; the last range may be short).
-  const int kc = ((g.K + g.k_split - 1) / g.k_split + 31) / 32 * 32;
-  const int kb = blockIdx.z * kc, ke = min(g.K, kb + kc);
-  const bool do_rs = g.rowsum && blockIdx.x == 0;
-  const int rs_r = threadIdx.x >> 2, rs_q = threadIdx.x & 3;   // 4 threads per row
-  float rs = 0.f;
-  f32x16 acc = f32x16{};
-  for (int k0 = kb; k0 < ke; k0 += kGemmK) {
-    stage_slice(As, g.A, g.lda_m, g.lda_k, m0, g.M, k0, ke);
-    stage_slice(Bs, g.B, g.ldb_n, g.ldb_k, n0, g.N, k0, ke);
+  // Range sums in range order (see the arithmetic of a product above).
+  const int per_w = (((g.K + 15) >> 4) + kSmallWaves - 1) / kSmallWaves;
+  f32x16 total = f32x16{}, acc = f32x16{};
+  int w = 0, next = per_w;                        // acc holds range w; range w + 1 starts at next
+  auto fold = [&]() {
+    total = w == 0 ? acc : total + acc;
+    acc = f32x16{};
+    ++w;
+    next += per_w;
+  };
+  for (int k0 = 0; k0 < g.K; k0 += kGemmK) {
+    stage_slice(As, g.A, g.lda_m, g.lda_k, m0, g.M, k0, g.K);
+    stage_slice(Bs, g.B, g.ldb_n, g.ldb_k, n0, g.N, k0, g.K);
     __syncthreads();
-    if (do_rs) {
-#pragma unroll
-      for (int c = 0; c < kGemmK / 4; ++c) rs += As[rs_r * kGemmLd + rs_q * (kGemmK / 4) + c];
-      static_assert(kGemmK == 128, "staging maps assume 128 K values per pass");
-    }
-    const int kn = min(kGemmK, ke - k0);           // MFMA steps past kn read zeros: skip them
+    const int kn = min(kGemmK, g.K - k0);          // steps past kn read zeros: skip them
     const float* ar = As + (wm * 32 + l32) * kGemmLd;
     const float* br = Bs + (wn * 32 + l32) * kGemmLd;
-    if constexpr (BF16) {
-      for (int kk = 0; kk < kn; kk += 16) {
+    for (int kk = 0; kk < kn; kk += 16) {
+      while (((k0 + kk) >> 4) >= next) fold();
+      if constexpr (BF16) {
         bf16x8 a, b;
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
@@ -132,75 +160,186 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
           b[v] = (__bf16)br[kk + 8 * h + v];
         }
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[kk + 8 * h + v], br[kk + 8 * h + v], acc,
+                                                     0, 0, 0);
       }
-    } else {
-      for (int kk = 0; kk < kn; kk += 2)
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[kk + h], br[kk + h], acc, 0, 0, 0);
     }
     __syncthreads();
   }
-  if (do_rs) {
-    // The row's 4 partial sums sit in 4 consecutive lanes: fixed-order pairs.
-    rs += __shfl_xor(rs, 1);
-    rs += __shfl_xor(rs, 2);
-    const int m = m0 + rs_r;
-    if (rs_q == 0 && m < g.M) {
-      if (g.k_split > 1) g.part_rs[(int64_t)blockIdx.z * g.M + m] = rs;
-      else g.rowsum[m] = rs;
-    }
-  }
+  while (w < kSmallWaves) fold();
   const int n = n0 + wn * 32 + l32;
   if (n >= g.N) return;
-  if (g.k_split > 1) {
-    float* P = g.part + (int64_t)blockIdx.z * g.M * g.N;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int m = m0 + wm * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-      if (m < g.M) P[(int64_t)m * g.N + n] = acc[i];
-    }
-    return;
-  }
-  const float bias = g.bias ? g.bias[n] : 0.f;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int m = m0 + wm * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-    if (m >= g.M) continue;
-    float z = acc[i] + bias;
-    const int64_t off = (int64_t)m * g.ldc + n;
-    if (g.act == 1) {
-      if (g.Z) g.Z[off] = z;
-      z = gelu_f(z);
-    } else if (g.act == 2) {
-      z *= gelu_grad_f(g.aux[(int64_t)m * g.ld_aux + n]);
-    }
-    g.C[off] = z;
+    if (m < g.M) gemm_store(g, m, n, total[i]);
   }
 }
 
-// Split-K results: C[m][n] = epilogue(sum over ranges in order); row sums
-// likewise (no epilogue).
-__global__ void gemm_reduce_kernel(GemmArgs g) {
+// Small products: a 32x32 tile of C per workgroup of kSmallWaves waves.
+// The K range of the workgroup (all of K, or range blockIdx.z of a split
+// product) is cut into 16-value steps, wave w taking range w of them.  In
+// step s, lane (r, h) of a wave needs X(row0 + r, 16 s + 8 h + v), v = 0..7,
+// of each operand X.  When the row index is the unit stride (or the operand
+// has one row) each lane loads its own values: a load instruction reads
+// consecutive addresses.  When k is the unit stride, the wave instead loads
+// its 32 rows x 64 k block along k (one row per instruction), writes it to
+// its own LDS area and reads its values back.  A wave loads up to
+// kSmallSteps steps per round, every load of the round issued before the
+// first wait.  The waves' partial tiles (and row sums) are added in wave
+// order through LDS (over the staging areas, after a barrier).
+constexpr int kStageLd = 68;                    // staged row: 64 k values + 4 (16-byte rows)
+constexpr int kStageFloats = 32 * kStageLd;     // one operand of one wave
+
+template <bool STAGED>
+struct SmallOperand {
+  const float* X;
+  int64_t ld_r, ld_k;
+  int row0, R;
+  float* stage;                                 // this wave's LDS area (staged only)
+};
+
+__host__ __device__ inline bool small_staged(int64_t ld_r, int64_t ld_k, int R) {
+  return ld_k == 1 && ld_r != 1 && R > 1;
+}
+
+// Issues the loads of a round (steps s0 ..) into raw[32], branch-free so
+// that both operands' loads are in flight together: load j reads row
+// row0 + j at k = 16 s0 + lane (staged), or row row0 + r at
+// k = 16 (s0 + j / 8) + 8 h + j % 8 (direct); clamped into the operand.
+// Offsets are 32-bit byte offsets from the operand's base (the launch
+// checks that every operand spans less than 4 GiB), so each load needs one
+// address register.
+template <bool STAGED>
+__device__ __forceinline__ void small_issue(const SmallOperand<STAGED>& o, int s0, int K, int lane,
+                                            float (&raw)[32]) {
+  const int r = lane & 31, h = lane >> 5;
+  const uint32_t ldr = (uint32_t)o.ld_r * 4u, ldk = (uint32_t)o.ld_k * 4u;
+  const char* base = reinterpret_cast<const char*>(o.X);
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const int row = o.row0 + (STAGED ? j : r);
+    const int k = STAGED ? s0 * 16 + lane : (s0 + (j >> 3)) * 16 + 8 * h + (j & 7);
+    const uint32_t off = (uint32_t)min(row, o.R - 1) * ldr + (uint32_t)min(k, K - 1) * ldk;
+    raw[j] = *reinterpret_cast<const float*>(base + off);
+  }
+}
+
+// The round's values of lane (r, h), zero outside rows < R, k < K and
+// steps < se.
+template <bool STAGED>
+__device__ __forceinline__ void small_finish(const SmallOperand<STAGED>& o, int s0, int se, int K,
+                                             int lane, const float (&raw)[32],
+                                             float (&val)[kSmallSteps][8]) {
+  const int r = lane & 31, h = lane >> 5;
+  if constexpr (STAGED) {
+    const int k = s0 * 16 + lane;
+    const bool kok = k < K && (k >> 4) < se;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) o.stage[j * kStageLd + lane] = keep_if(raw[j], kok && o.row0 + j < o.R);
+#pragma unroll
+    for (int i = 0; i < kSmallSteps; ++i)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) val[i][v] = o.stage[r * kStageLd + i * 16 + 8 * h + v];
+  } else {
+    const bool rok = o.row0 + r < o.R;
+#pragma unroll
+    for (int i = 0; i < kSmallSteps; ++i)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int k = (s0 + i) * 16 + 8 * h + v;
+        val[i][v] = keep_if(raw[i * 8 + v], rok && k < K && s0 + i < se);
+      }
+  }
+}
+
+size_t small_lds_bytes(const GemmArgs& g) {
+  const int st = (small_staged(g.lda_m, g.lda_k, g.M) ? 1 : 0) +
+                 (small_staged(g.ldb_n, g.ldb_k, g.N) ? 1 : 0);
+  const size_t stage = (size_t)kSmallWaves * st * kStageFloats;
+  const size_t red = (size_t)kSmallWaves * 32 * 32;
+  return ((size_t)kSmallWaves * 64 + (stage > red ? stage : red)) * sizeof(float);
+}
+
+template <bool BF16, bool SA, bool SB>
+__global__ __launch_bounds__(64 * kSmallWaves) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void gemm_small_kernel(GemmArgs g) {
+  extern __shared__ float small_lds[];
+  float* red_rs = small_lds;                            // [waves][64]
+  float* red = small_lds + kSmallWaves * 64;            // [waves][32 * 32], over the staging areas
   if (g.skip && *g.skip) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t MN = (int64_t)g.M * g.N;
-  if (i < MN) {
-    float z = 0.f;
-    for (int k = 0; k < g.k_split; ++k) z += g.part[(int64_t)k * MN + i];
-    const int m = (int)(i / g.N), n = (int)(i - (int64_t)m * g.N);
-    if (g.bias) z += g.bias[n];
-    const int64_t off = (int64_t)m * g.ldc + n;
-    if (g.act == 1) {
-      if (g.Z) g.Z[off] = z;
-      z = gelu_f(z);
-    } else if (g.act == 2) {
-      z *= gelu_grad_f(g.aux[(int64_t)m * g.ld_aux + n]);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int r = lane & 31, h = lane >> 5;
+  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  const int steps = (g.K + 15) >> 4;
+  const int per_z = (steps + g.k_split - 1) / g.k_split;
+  const int zb = min(steps, (int)blockIdx.z * per_z), ze = min(steps, zb + per_z);
+  const int per_w = (ze - zb + kSmallWaves - 1) / kSmallWaves;
+  const int wb = min(ze, zb + wave * per_w), we = min(ze, wb + per_w);
+  float* area = red + wave * ((SA ? 1 : 0) + (SB ? 1 : 0)) * kStageFloats;
+  const SmallOperand<SA> oa{g.A, g.lda_m, g.lda_k, m0, g.M, area};
+  const SmallOperand<SB> ob{g.B, g.ldb_n, g.ldb_k, n0, g.N, area + (SA ? kStageFloats : 0)};
+  f32x16 acc = f32x16{};
+  float rs = 0.f;
+  for (int s0 = wb; s0 < we; s0 += kSmallSteps) {
+    float ra[32], rb[32];
+    small_issue(oa, s0, g.K, lane, ra);
+    small_issue(ob, s0, g.K, lane, rb);
+    __builtin_amdgcn_sched_barrier(0);   // keep every load ahead of the first use
+    float av[kSmallSteps][8], bv[kSmallSteps][8];
+    small_finish(oa, s0, we, g.K, lane, ra, av);
+    small_finish(ob, s0, we, g.K, lane, rb, bv);
+    // Steps past the wave's range hold zeros: running their MFMAs keeps the
+    // code free of branches.
+#pragma unroll
+    for (int i = 0; i < kSmallSteps; ++i) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) rs += av[i][v];
+      if constexpr (BF16) {
+        bf16x8 a, b;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          a[v] = (__bf16)av[i][v];
+          b[v] = (__bf16)bv[i][v];
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][v], bv[i][v], acc, 0, 0, 0);
+      }
     }
-    g.C[off] = z;
-  } else if (g.rowsum && i < MN + g.M) {
-    const int m = (int)(i - MN);
-    float s = 0.f;
-    for (int k = 0; k < g.k_split; ++k) s += g.part_rs[(int64_t)k * g.M + m];
-    g.rowsum[m] = s;
+  }
+  __syncthreads();   // every wave is done with its staging area
+  // Accumulator register i of lane (r, h) is C row 8 (i / 4) + 4 h + i % 4,
+  // column r.
+  float* rw = red + wave * 32 * 32;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) rw[(8 * (i >> 2) + 4 * h + (i & 3)) * 32 + r] = acc[i];
+  red_rs[wave * 64 + lane] = rs;
+  __syncthreads();
+  const bool split = g.part != nullptr;
+  for (int o = threadIdx.x; o < 32 * 32; o += 64 * kSmallWaves) {
+    const int mm = m0 + (o >> 5), nn = n0 + (o & 31);
+    if (mm >= g.M || nn >= g.N) continue;
+    float z = red[o];
+#pragma unroll
+    for (int w = 1; w < kSmallWaves; ++w) z += red[w * 32 * 32 + o];
+    if (split) g.part[(int64_t)blockIdx.z * g.part_ld + (int64_t)mm * g.ldc + nn] = z;
+    else gemm_store(g, mm, nn, z);
+  }
+  // Row sums of A over the range (the first column tile computes them):
+  // the two lane halves of each wave, waves in order.
+  if (g.rowsum_part && blockIdx.x == 0 && threadIdx.x < 32 && m0 + (int)threadIdx.x < g.M) {
+    const int t = threadIdx.x;
+    float v = 0.f;
+#pragma unroll
+    for (int w = 0; w < kSmallWaves; ++w) v += red_rs[w * 64 + t] + red_rs[w * 64 + t + 32];
+    g.rowsum_part[(int64_t)blockIdx.z * g.part_ld + m0 + t] = v;
   }
 }
 
@@ -218,17 +357,51 @@ static hipError_t launch_gemm_t(const GemmArgs& g, const dim3& grid, hipStream_t
   return hipGetLastError();
 }
 
+template <bool BF16, bool SA, bool SB>
+static hipError_t launch_small_sab(const GemmArgs& g, const dim3& grid, size_t lds, hipStream_t s) {
+  static bool lds_set = false;   // one attribute call per instantiation
+  if (!lds_set) {
+    const int most = (int)((kSmallWaves * 64 + kSmallWaves * 2 * kStageFloats) * sizeof(float));
+    const hipError_t e = hipFuncSetAttribute((const void*)gemm_small_kernel<BF16, SA, SB>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, most);
+    if (e != hipSuccess) return e;
+    lds_set = true;
+  }
+  hipLaunchKernelGGL((gemm_small_kernel<BF16, SA, SB>), grid, dim3(64 * kSmallWaves), lds, s, g);
+  return hipGetLastError();
+}
+
+template <bool BF16>
+static hipError_t launch_small_t(const GemmArgs& g, bool sa, bool sb, const dim3& grid, size_t lds,
+                                 hipStream_t s) {
+  if (sa) return sb ? launch_small_sab<BF16, true, true>(g, grid, lds, s)
+                    : launch_small_sab<BF16, true, false>(g, grid, lds, s);
+  return sb ? launch_small_sab<BF16, false, true>(g, grid, lds, s)
+            : launch_small_sab<BF16, false, false>(g, grid, lds, s);
+}
+
 hipError_t launch_gemm(const GemmArgs& g0, bool bf16, hipStream_t s) {
   GemmArgs g = g0;
   if (g.k_split < 1) g.k_split = 1;
-  if (g.k_split > 1 && (!g.part || (g.rowsum && !g.part_rs))) return hipErrorInvalidValue;
-  const dim3 grid((g.N + kGemmTile - 1) / kGemmTile, (g.M + kGemmTile - 1) / kGemmTile,
-                  g.k_split);
-  hipError_t e = bf16 ? launch_gemm_t<true>(g, grid, s) : launch_gemm_t<false>(g, grid, s);
-  if (e != hipSuccess || g.k_split == 1) return e;
-  const int64_t n = (int64_t)g.M * g.N + (g.rowsum ? g.M : 0);
-  hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
-  return hipGetLastError();
+  if (g.k_split > 1 && !g.part) return hipErrorInvalidValue;
+  if (g.rowsum_part && !g.part) return hipErrorInvalidValue;
+  // Operand spans in bytes (the small-product kernel uses 32-bit offsets).
+  const auto span = [](int64_t rows, int64_t ld_r, int64_t K, int64_t ld_k) {
+    return ((rows - 1) * ld_r + (K - 1) * ld_k + 1) * (int64_t)sizeof(float);
+  };
+  const bool fits = g.lda_m >= 0 && g.lda_k >= 0 && g.ldb_n >= 0 && g.ldb_k >= 0 &&
+                    span(g.M, g.lda_m, g.K, g.lda_k) < (int64_t)UINT32_MAX &&
+                    span(g.N, g.ldb_n, g.K, g.ldb_k) < (int64_t)UINT32_MAX;
+  if (g.part && !fits) return hipErrorInvalidValue;
+  if (g.part || (g.M <= kSmallMaxM && fits)) {
+    const dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, g.k_split);
+    const size_t lds = small_lds_bytes(g);
+    const bool sa = small_staged(g.lda_m, g.lda_k, g.M), sb = small_staged(g.ldb_n, g.ldb_k, g.N);
+    return bf16 ? launch_small_t<true>(g, sa, sb, grid, lds, s)
+                : launch_small_t<false>(g, sa, sb, grid, lds, s);
+  }
+  const dim3 grid((g.N + kGemmTile - 1) / kGemmTile, (g.M + kGemmTile - 1) / kGemmTile, 1);
+  return bf16 ? launch_gemm_t<true>(g, grid, s) : launch_gemm_t<false>(g, grid, s);
 }
 
 // Output layer, one wave per row b: y_b = b3 + sum_j H2[b][j] w3[j] in
@@ -268,11 +441,20 @@ hipError_t launch_out_layer(const float* H2, const float* w3, const float* b3, i
   return hipGetLastError();
 }
 
-// Adam (Kingma & Ba) with bias correction on float32 parameters.  The step
-// counter lives on the device (so a captured graph advances it on every
-// replay); the training step's output-layer launch has already advanced it.
-__global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float lr,
-                            const SurrogateState* st, const int32_t* skip) {
+// Adam (Kingma & Ba) with bias correction on float32 parameters.  The
+// gradient of parameter i is the sum of the ks split ranges part[z * n + i]
+// in order z = 0, 1, ... (the weight-gradient products write them).  The
+// step counter lives on the device (so a captured graph advances it on
+// every replay); the training step's output-layer launch has already
+// advanced it.
+__device__ __forceinline__ float sum_ranges(const float* part, int ks, int64_t n, int64_t i) {
+  float gi = part[i];
+  for (int z = 1; z < ks; ++z) gi += part[(int64_t)z * n + i];
+  return gi;
+}
+
+__global__ void adam_kernel(float* p, const float* part, int ks, float* m, float* v, int64_t n,
+                            float lr, const SurrogateState* st, const int32_t* skip) {
   if (skip && *skip) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -280,7 +462,7 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_
   const float c1 = 1.f - powf(0.9f, (float)step);
   const float c2 = 1.f - powf(0.999f, (float)step);
   const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
-  const float gi = g[i];
+  const float gi = sum_ranges(part, ks, n, i);
   const float mi = beta1 * m[i] + (1.f - beta1) * gi;
   const float vi = beta2 * v[i] + (1.f - beta2) * gi * gi;
   m[i] = mi;
@@ -288,10 +470,21 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
-                       SurrogateState* st, const int32_t* skip, hipStream_t s) {
-  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v,
-                     n, lr, (const SurrogateState*)st, skip);
+hipError_t launch_adam(float* p, const float* part, int ks, float* m, float* v, int64_t n,
+                       float lr, SurrogateState* st, const int32_t* skip, hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, part, ks,
+                     m, v, n, lr, (const SurrogateState*)st, skip);
+  return hipGetLastError();
+}
+
+__global__ void sum_ranges_kernel(float* g, const float* part, int ks, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) g[i] = sum_ranges(part, ks, n, i);
+}
+
+hipError_t launch_sum_ranges(float* g, const float* part, int ks, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(sum_ranges_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g,
+                     part, ks, n);
   return hipGetLastError();
 }
 

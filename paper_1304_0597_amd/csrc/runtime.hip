@@ -163,7 +163,7 @@ struct game_surrogate_ctx {
   uint64_t* sorted;
   float *audit_genes, *audit_pred, *audit_exact, *H1a, *H2a;
   // split-K partial products of the weight gradients
-  float *kpart, *kpart_rs;
+  float* kpart;              // [k ranges][n_params] weight-gradient ranges
 };
 
 namespace {
@@ -234,7 +234,7 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // ----------------------------------------------------------- surrogate
 struct SurLayout {
   size_t st, params, grads, m, v, Xb, tb, Z1, H1, Z2, H2, y, dy, dZ2, dZ1, H1c, H2c, yc, ag, at,
-      cand, rank, sorted, aug, aup, aue, H1a, H2a, kpart, kprs, total;
+      cand, rank, sorted, aug, aup, aue, H1a, H2a, kpart, total;
   int64_t n_params;
 };
 
@@ -273,9 +273,7 @@ SurLayout sur_layout(const game_surrogate_config* c, int32_t n_in, int32_t max_b
   L.aue = take(A * 4);
   L.H1a = take(A * H * 4);
   L.H2a = take(A * H * 4);
-  const size_t ks = (size_t)gemm_k_split((int)B);
-  L.kpart = take(ks > 1 ? ks * std::max(H * (size_t)n_in, H * H) * 4 : 0);
-  L.kprs = take(ks > 1 ? ks * H * 4 : 0);
+  L.kpart = take((size_t)gemm_k_split((int)B) * P);
   L.total = off;
   return L;
 }
@@ -339,40 +337,43 @@ int sur_forward(game_surrogate_ctx* s, const float* X, int n, float* Z1, float* 
   return GAME_OK;
 }
 
-// Gradients of mean((y - t)^2) over the n rows in s->Xb / s->tb into
-// s->grads; for_adam: this is a training step (advances the step count).
+// Gradients of mean((y - t)^2) over the n rows in s->Xb / s->tb, as *ks
+// ranges in s->kpart ([range][n_params], parameter order; the gradient is
+// their sum in range order); for_adam: this is a training step (advances
+// the step count).
 int sur_gradients(game_surrogate_ctx* s, int n, const int32_t* skip, hipStream_t st,
-                  bool for_adam) {
+                  bool for_adam, int* ks_out) {
   const bool bf16 = !s->cfg.fp32_operands;
   const int H = s->H, ni = s->n_in;
   int rc = sur_forward(s, s->Xb, n, s->Z1, s->H1, s->Z2, s->H2, s->y, skip, st, s->tb,
                        for_adam ? &s->st->step : nullptr);
   if (rc) return rc;
   const SurParams p = split_params(s, s->params);
-  const SurParams g = split_params(s, s->grads);
-  // Weight gradients sum over the n minibatch rows: split K when n is long
-  // (n <= cfg.minibatch, for which the partial buffers are sized).  Each
-  // bias gradient is the row sum of the product's A operand.
-  const int ks = std::min(gemm_k_split(n), gemm_k_split(s->cfg.minibatch));
+  const SurParams gp = split_params(s, s->kpart);
+  // Weight gradients sum over the n minibatch rows in ks ranges (n <=
+  // cfg.minibatch, for which kpart is sized).  Each bias gradient is the
+  // row sum of the product's A operand.
+  const int ks = gemm_k_split(n);
+  *ks_out = ks;
   auto wgrad = [&](GemmArgs g, float* bias_grad) {
-    g.rowsum = bias_grad;
+    g.part = g.C;
+    g.rowsum_part = bias_grad;
+    g.part_ld = s->n_params;
     g.k_split = ks;
-    g.part = s->kpart;
-    g.part_rs = s->kpart_rs;
     return launch_gemm(g, bf16, st);
   };
   // dw3 = dy^T H2, db3 = sum dy
-  GAME_HIP(wgrad(gemm(s->dy, 0, 1, s->H2, 1, H, g.w3, H, 1, H, n, nullptr, 0, nullptr, nullptr, 0,
-                      skip), g.b3));
+  GAME_HIP(wgrad(gemm(s->dy, 0, 1, s->H2, 1, H, gp.w3, H, 1, H, n, nullptr, 0, nullptr, nullptr, 0,
+                      skip), gp.b3));
   // dW2 = dZ2^T H1, db2 = column sums of dZ2
-  GAME_HIP(wgrad(gemm(s->dZ2, 1, H, s->H1, 1, H, g.W2, H, H, H, n, nullptr, 0, nullptr, nullptr,
-                      0, skip), g.b2));
+  GAME_HIP(wgrad(gemm(s->dZ2, 1, H, s->H1, 1, H, gp.W2, H, H, H, n, nullptr, 0, nullptr, nullptr,
+                      0, skip), gp.b2));
   // dZ1 = (dZ2 W2) * gelu'(Z1)
   GAME_HIP(launch_gemm(gemm(s->dZ2, H, 1, p.W2, 1, H, s->dZ1, H, n, H, H, nullptr, 2, nullptr,
                             s->Z1, H, skip), bf16, st));
   // dW1 = dZ1^T X, db1 = column sums of dZ1
-  GAME_HIP(wgrad(gemm(s->dZ1, 1, H, s->Xb, 1, ni, g.W1, ni, H, ni, n, nullptr, 0, nullptr, nullptr,
-                      0, skip), g.b1));
+  GAME_HIP(wgrad(gemm(s->dZ1, 1, H, s->Xb, 1, ni, gp.W1, ni, H, ni, n, nullptr, 0, nullptr, nullptr,
+                      0, skip), gp.b1));
   return GAME_OK;
 }
 
@@ -402,9 +403,11 @@ int enqueue_screening(game_ctx* h, hipStream_t s) {
   for (int step = 0; step < c.train_steps; ++step) {
     GAME_HIP(launch_sample_minibatch(sr->arch_genes, sr->arch_target, K, sr->st, h->state, c.seed,
                                      step, c.minibatch, sr->Xb, sr->tb, s));
-    int rc = sur_gradients(sr, c.minibatch, stop, s, true);
+    int ks = 1;
+    int rc = sur_gradients(sr, c.minibatch, stop, s, true, &ks);
     if (rc) return rc;
-    GAME_HIP(launch_adam(sr->params, sr->grads, sr->m, sr->v, sr->n_params, c.lr, sr->st, stop, s));
+    GAME_HIP(launch_adam(sr->params, sr->kpart, ks, sr->m, sr->v, sr->n_params, c.lr, sr->st, stop,
+                         s));
   }
   const int C = c.oversample * (P - E);
   GAArgs ga = ga_args(&h->cfg, K);
@@ -964,7 +967,6 @@ int game_surrogate_create(const game_surrogate_config* c, int32_t n_genes, int32
   s->H1a = (float*)(b + L.H1a);
   s->H2a = (float*)(b + L.H2a);
   s->kpart = (float*)(b + L.kpart);
-  s->kpart_rs = (float*)(b + L.kprs);
   hipError_t e = launch_fill_zero((float*)s->st, sizeof(SurrogateState) / sizeof(float), s->stream);
   if (e == hipSuccess) e = launch_fill_zero(s->m, s->n_params, s->stream);
   if (e == hipSuccess) e = launch_fill_zero(s->v, s->n_params, s->stream);
@@ -1017,8 +1019,10 @@ int game_surrogate_gradients(game_surrogate_t s, const float* genes, const float
   GAME_HIP(hipMemcpyAsync(s->Xb, genes, sizeof(float) * n * s->n_in, hipMemcpyDeviceToDevice,
                           s->stream));
   GAME_HIP(hipMemcpyAsync(s->tb, target, sizeof(float) * n, hipMemcpyDeviceToDevice, s->stream));
-  int rc = sur_gradients(s, n, nullptr, s->stream, false);
+  int ks = 1;
+  int rc = sur_gradients(s, n, nullptr, s->stream, false, &ks);
   if (rc) return rc;
+  GAME_HIP(launch_sum_ranges(s->grads, s->kpart, ks, s->n_params, s->stream));
   GAME_HIP(hipMemcpyAsync(grads, s->grads, sizeof(float) * s->n_params, hipMemcpyDeviceToDevice,
                           s->stream));
   if (y) GAME_HIP(hipMemcpyAsync(y, s->y, sizeof(float) * n, hipMemcpyDeviceToDevice, s->stream));
@@ -1033,9 +1037,10 @@ int game_surrogate_train_step(game_surrogate_t s, const float* genes, const floa
   GAME_HIP(hipMemcpyAsync(s->Xb, genes, sizeof(float) * n * s->n_in, hipMemcpyDeviceToDevice,
                           s->stream));
   GAME_HIP(hipMemcpyAsync(s->tb, target, sizeof(float) * n, hipMemcpyDeviceToDevice, s->stream));
-  int rc = sur_gradients(s, n, nullptr, s->stream, true);
+  int ks = 1;
+  int rc = sur_gradients(s, n, nullptr, s->stream, true, &ks);
   if (rc) return rc;
-  GAME_HIP(launch_adam(s->params, s->grads, s->m, s->v, s->n_params, s->cfg.lr, s->st, nullptr,
+  GAME_HIP(launch_adam(s->params, s->kpart, ks, s->m, s->v, s->n_params, s->cfg.lr, s->st, nullptr,
                        s->stream));
   return GAME_OK;
 }

@@ -96,6 +96,27 @@ def test_forward_and_gradients_match_oracle(gg, fp32, n_in, H, B):
     s.close()
 
 
+@pytest.mark.parametrize("fp32", [True, False])
+def test_forward_on_both_product_kernels(gg, fp32):
+    """Up to 4,096 rows the products run on the small-tile kernel, above it
+    on the LDS-tiled one (the forward over all oversampled candidates): both
+    against the oracle, on a ragged row count."""
+    rng = np.random.default_rng(11)
+    n_in, H = 161, 64
+    s = make(gg, n_in, fp32, H=H, minibatch=64, max_batch=4141)
+    flat = s.params().cpu().numpy()
+    params = [np.asarray(x, np.float64) for x in split(flat, n_in, H)]
+    X = rng.uniform(-1, 1, (4141, n_in)).astype(np.float32)
+    y_ref, _ = mlp.forward(params, X)
+    for n in (4096, 4141):
+        y = s.predict(torch.from_numpy(X[:n]).cuda()).cpu().numpy()
+        if fp32:
+            assert rel_l2(y, y_ref[:n]) < 1e-5, n
+        else:
+            assert rel_l2(y, y_ref[:n]) < 2e-2 and cosine(y, y_ref[:n]) > 0.999, n
+    s.close()
+
+
 def test_adam_step_matches_oracle(gg):
     rng = np.random.default_rng(5)
     n_in, H, B = 29, 32, 64
