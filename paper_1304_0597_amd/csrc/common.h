@@ -304,6 +304,9 @@ inline int gemm_k_split(int K) {
   return r < 1 ? 1 : (r > 8 ? 8 : r);
 }
 hipError_t launch_gemm(const GemmArgs& g, bool bf16, hipStream_t s);
+// Two independent small products with the same operand layouts and k_split
+// in one launch.
+hipError_t launch_gemm_pair(const GemmArgs& a, const GemmArgs& b, bool bf16, hipStream_t s);
 // Output layer (and with t set, its backward); see out_layer_kernel.
 hipError_t launch_out_layer(const float* H2, const float* w3, const float* b3, int B, int H,
                             float* y, const float* t, const float* Z2, float* dy, float* dZ2,
@@ -321,6 +324,30 @@ struct SurrogateState {
   int32_t skip;             // 1 when the candidates need no full scoring (stopped or not used)
   int32_t pad[7];
 };
+// Gradient of parameter i: the sum of the ks split ranges part[z * n + i]
+// in order z = 0, 1, ...
+__device__ __forceinline__ float sum_ranges(const float* part, int ks, int64_t n, int64_t i) {
+  float gi = part[i];
+  for (int z = 1; z < ks; ++z) gi += part[(int64_t)z * n + i];
+  return gi;
+}
+
+// Adam (Kingma & Ba) with bias correction, parameter i, at Adam step `step`
+// (1 for the first update).  The moment updates are explicit FMAs, so the
+// result does not depend on the translation unit's contraction setting.
+__device__ __forceinline__ void adam_update(float* p, const float* part, int ks, float* m, float* v,
+                                            int64_t n, float lr, int step, int64_t i) {
+  const float c1 = 1.f - powf(0.9f, (float)step);
+  const float c2 = 1.f - powf(0.999f, (float)step);
+  const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+  const float gi = sum_ranges(part, ks, n, i);
+  const float mi = fmaf(beta1, m[i], (1.f - beta1) * gi);
+  const float vi = fmaf(beta2, v[i], ((1.f - beta2) * gi) * gi);
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
 // Adam on n parameters whose gradient is the sum of ks ranges
 // part[z * n + i], added in order z = 0, 1, ...
 hipError_t launch_adam(float* p, const float* part, int ks, float* m, float* v, int64_t n,
@@ -348,6 +375,12 @@ hipError_t launch_archive_stats(const float* target, SurrogateState* st, const R
 hipError_t launch_sample_minibatch(const float* genes, const float* target, int32_t K,
                                    const SurrogateState* st, const RunState* run, uint64_t seed,
                                    int32_t step, int32_t B, float* Xb, float* tb, hipStream_t s);
+// The Adam update of a training step and the minibatch draw of the next one
+// (independent work) in one launch.
+hipError_t launch_adam_sample(float* p, const float* part, int ks, float* m, float* v, int64_t n,
+                              float lr, SurrogateState* st, const int32_t* skip, const float* genes,
+                              const float* target, int32_t K, const RunState* run, uint64_t seed,
+                              int32_t next_step, int32_t B, float* Xb, float* tb, hipStream_t s);
 hipError_t launch_audit_pick(const float* cand, int32_t C, int32_t K, const RunState* run,
                              uint64_t seed, int32_t A, float* genes, hipStream_t s);
 hipError_t launch_spearman_gate(const float* pred, const float* exact, int32_t A, float rho_min,

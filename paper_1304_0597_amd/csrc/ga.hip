@@ -656,17 +656,54 @@ hipError_t launch_archive_stats(const float* target, SurrogateState* st, const R
 // Minibatch of B archive rows drawn with replacement: row b is
 // (u32 * count) >> 32 with u32 = lo32(o0) of key (seed, 3), counter
 // (generation, 1 + step, b, 0); targets standardised.
-__global__ void sample_minibatch_kernel(const float* genes, const float* target, int K,
-                                        const SurrogateState* st, const RunState* run,
-                                        uint64_t seed, int step, int B, float* Xb, float* tb) {
-  if (run->stop) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sample_minibatch_body(int64_t i, const float* genes,
+                                                      const float* target, int K,
+                                                      const SurrogateState* st,
+                                                      const RunState* run, uint64_t seed, int step,
+                                                      int B, float* Xb, float* tb) {
   if (i >= (int64_t)B * K) return;
   const int b = (int)(i / K), g = (int)(i - (int64_t)b * K);
   const U64x4 r = draw(seed, 3, (uint64_t)run->evaluated, (uint64_t)(1 + step), (uint64_t)b);
   const int idx = (int)(((r.o0 & 0xFFFFFFFFull) * (uint64_t)st->count) >> 32);
   Xb[i] = genes[(int64_t)idx * K + g];
   if (g == 0) tb[b] = (target[idx] - st->mean) * st->inv_std;
+}
+
+__global__ void sample_minibatch_kernel(const float* genes, const float* target, int K,
+                                        const SurrogateState* st, const RunState* run,
+                                        uint64_t seed, int step, int B, float* Xb, float* tb) {
+  if (run->stop) return;
+  sample_minibatch_body((int64_t)blockIdx.x * blockDim.x + threadIdx.x, genes, target, K, st, run,
+                        seed, step, B, Xb, tb);
+}
+
+// Workgroups [0, adam_blocks) update the parameters; the rest draw the next
+// step's minibatch (Xb and tb are not read by the update).
+__global__ void adam_sample_kernel(float* p, const float* part, int ks, float* m, float* v,
+                                   int64_t n, float lr, SurrogateState* st, const int32_t* skip,
+                                   int adam_blocks, const float* genes, const float* target, int K,
+                                   const RunState* run, uint64_t seed, int next_step, int B,
+                                   float* Xb, float* tb) {
+  if (skip && *skip) return;
+  if ((int)blockIdx.x < adam_blocks) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) adam_update(p, part, ks, m, v, n, lr, st->step, i);
+    return;
+  }
+  sample_minibatch_body((int64_t)(blockIdx.x - adam_blocks) * blockDim.x + threadIdx.x, genes,
+                        target, K, st, run, seed, next_step, B, Xb, tb);
+}
+
+hipError_t launch_adam_sample(float* p, const float* part, int ks, float* m, float* v, int64_t n,
+                              float lr, SurrogateState* st, const int32_t* skip, const float* genes,
+                              const float* target, int32_t K, const RunState* run, uint64_t seed,
+                              int32_t next_step, int32_t B, float* Xb, float* tb, hipStream_t s) {
+  const int adam_blocks = (int)((n + 255) / 256);
+  const int sample_blocks = (int)(((int64_t)B * K + 255) / 256);
+  hipLaunchKernelGGL(adam_sample_kernel, dim3((unsigned)(adam_blocks + sample_blocks)), dim3(256),
+                     0, s, p, part, ks, m, v, n, lr, st, skip, adam_blocks, genes, target, K, run,
+                     seed, next_step, B, Xb, tb);
+  return hipGetLastError();
 }
 
 hipError_t launch_sample_minibatch(const float* genes, const float* target, int32_t K,

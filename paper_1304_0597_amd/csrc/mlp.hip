@@ -23,6 +23,8 @@
 // columns and k read as zero in both.  Results never depend on scheduling.
 #include <math.h>
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace game {
@@ -264,17 +266,28 @@ size_t small_lds_bytes(const GemmArgs& g) {
   return ((size_t)kSmallWaves * 64 + (stage > red ? stage : red)) * sizeof(float);
 }
 
+// One launch may carry two independent products of the same operand
+// layouts (row tiles [0, ty0) serve g[0], the rest g[1]).
+struct GemmPair {
+  GemmArgs g[2];
+  int32_t ty0;
+};
+
 template <bool BF16, bool SA, bool SB>
 __global__ __launch_bounds__(64 * kSmallWaves) __attribute__((amdgpu_waves_per_eu(1, 2)))
-void gemm_small_kernel(GemmArgs g) {
+void gemm_small_kernel(GemmPair gp) {
   extern __shared__ float small_lds[];
   float* red_rs = small_lds;                            // [waves][64]
   float* red = small_lds + kSmallWaves * 64;            // [waves][32 * 32], over the staging areas
+  const int pi = (int)blockIdx.y >= gp.ty0 ? 1 : 0;
+  const GemmArgs& g = gp.g[pi];
+  const int by = (int)blockIdx.y - (pi ? gp.ty0 : 0);
   if (g.skip && *g.skip) return;
+  if ((int)blockIdx.x * 32 >= g.N || by * 32 >= g.M) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int r = lane & 31, h = lane >> 5;
-  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  const int m0 = by * 32, n0 = blockIdx.x * 32;
   const int steps = (g.K + 15) >> 4;
   const int per_z = (steps + g.k_split - 1) / g.k_split;
   const int zb = min(steps, (int)blockIdx.z * per_z), ze = min(steps, zb + per_z);
@@ -358,7 +371,7 @@ static hipError_t launch_gemm_t(const GemmArgs& g, const dim3& grid, hipStream_t
 }
 
 template <bool BF16, bool SA, bool SB>
-static hipError_t launch_small_sab(const GemmArgs& g, const dim3& grid, size_t lds, hipStream_t s) {
+static hipError_t launch_small_sab(const GemmPair& g, const dim3& grid, size_t lds, hipStream_t s) {
   static bool lds_set = false;   // one attribute call per instantiation
   if (!lds_set) {
     const int most = (int)((kSmallWaves * 64 + kSmallWaves * 2 * kStageFloats) * sizeof(float));
@@ -372,7 +385,7 @@ static hipError_t launch_small_sab(const GemmArgs& g, const dim3& grid, size_t l
 }
 
 template <bool BF16>
-static hipError_t launch_small_t(const GemmArgs& g, bool sa, bool sb, const dim3& grid, size_t lds,
+static hipError_t launch_small_t(const GemmPair& g, bool sa, bool sb, const dim3& grid, size_t lds,
                                  hipStream_t s) {
   if (sa) return sb ? launch_small_sab<BF16, true, true>(g, grid, lds, s)
                     : launch_small_sab<BF16, true, false>(g, grid, lds, s);
@@ -380,8 +393,8 @@ static hipError_t launch_small_t(const GemmArgs& g, bool sa, bool sb, const dim3
             : launch_small_sab<BF16, false, false>(g, grid, lds, s);
 }
 
-hipError_t launch_gemm(const GemmArgs& g0, bool bf16, hipStream_t s) {
-  GemmArgs g = g0;
+// Checks a product's arguments; small: it runs on gemm_small_kernel.
+static hipError_t check_gemm(GemmArgs& g, bool* small) {
   if (g.k_split < 1) g.k_split = 1;
   if (g.k_split > 1 && !g.part) return hipErrorInvalidValue;
   if (g.rowsum_part && !g.part) return hipErrorInvalidValue;
@@ -393,15 +406,47 @@ hipError_t launch_gemm(const GemmArgs& g0, bool bf16, hipStream_t s) {
                     span(g.M, g.lda_m, g.K, g.lda_k) < (int64_t)UINT32_MAX &&
                     span(g.N, g.ldb_n, g.K, g.ldb_k) < (int64_t)UINT32_MAX;
   if (g.part && !fits) return hipErrorInvalidValue;
-  if (g.part || (g.M <= kSmallMaxM && fits)) {
-    const dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, g.k_split);
-    const size_t lds = small_lds_bytes(g);
+  *small = g.part || (g.M <= kSmallMaxM && fits);
+  return hipSuccess;
+}
+
+hipError_t launch_gemm(const GemmArgs& g0, bool bf16, hipStream_t s) {
+  GemmArgs g = g0;
+  bool small = false;
+  const hipError_t e = check_gemm(g, &small);
+  if (e != hipSuccess) return e;
+  if (small) {
+    GemmPair gp{};
+    gp.g[0] = g;
+    gp.g[1] = g;
+    gp.ty0 = (g.M + 31) / 32;
+    const dim3 grid((g.N + 31) / 32, gp.ty0, g.k_split);
     const bool sa = small_staged(g.lda_m, g.lda_k, g.M), sb = small_staged(g.ldb_n, g.ldb_k, g.N);
-    return bf16 ? launch_small_t<true>(g, sa, sb, grid, lds, s)
-                : launch_small_t<false>(g, sa, sb, grid, lds, s);
+    return bf16 ? launch_small_t<true>(gp, sa, sb, grid, small_lds_bytes(g), s)
+                : launch_small_t<false>(gp, sa, sb, grid, small_lds_bytes(g), s);
   }
   const dim3 grid((g.N + kGemmTile - 1) / kGemmTile, (g.M + kGemmTile - 1) / kGemmTile, 1);
   return bf16 ? launch_gemm_t<true>(g, grid, s) : launch_gemm_t<false>(g, grid, s);
+}
+
+hipError_t launch_gemm_pair(const GemmArgs& a0, const GemmArgs& b0, bool bf16, hipStream_t s) {
+  GemmArgs a = a0, b = b0;
+  bool sm_a = false, sm_b = false;
+  hipError_t e = check_gemm(a, &sm_a);
+  if (e == hipSuccess) e = check_gemm(b, &sm_b);
+  if (e != hipSuccess) return e;
+  const bool sa = small_staged(a.lda_m, a.lda_k, a.M), sb = small_staged(a.ldb_n, a.ldb_k, a.N);
+  if (!sm_a || !sm_b || a.k_split != b.k_split || sa != small_staged(b.lda_m, b.lda_k, b.M) ||
+      sb != small_staged(b.ldb_n, b.ldb_k, b.N))
+    return hipErrorInvalidValue;
+  GemmPair gp{};
+  gp.g[0] = a;
+  gp.g[1] = b;
+  gp.ty0 = (a.M + 31) / 32;
+  const dim3 grid((std::max(a.N, b.N) + 31) / 32, gp.ty0 + (b.M + 31) / 32, a.k_split);
+  const size_t lds = std::max(small_lds_bytes(a), small_lds_bytes(b));
+  return bf16 ? launch_small_t<true>(gp, sa, sb, grid, lds, s)
+              : launch_small_t<false>(gp, sa, sb, grid, lds, s);
 }
 
 // Output layer, one wave per row b: y_b = b3 + sum_j H2[b][j] w3[j] in
@@ -447,27 +492,11 @@ hipError_t launch_out_layer(const float* H2, const float* w3, const float* b3, i
 // step counter lives on the device (so a captured graph advances it on
 // every replay); the training step's output-layer launch has already
 // advanced it.
-__device__ __forceinline__ float sum_ranges(const float* part, int ks, int64_t n, int64_t i) {
-  float gi = part[i];
-  for (int z = 1; z < ks; ++z) gi += part[(int64_t)z * n + i];
-  return gi;
-}
-
 __global__ void adam_kernel(float* p, const float* part, int ks, float* m, float* v, int64_t n,
                             float lr, const SurrogateState* st, const int32_t* skip) {
   if (skip && *skip) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int step = st->step;
-  const float c1 = 1.f - powf(0.9f, (float)step);
-  const float c2 = 1.f - powf(0.999f, (float)step);
-  const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
-  const float gi = sum_ranges(part, ks, n, i);
-  const float mi = beta1 * m[i] + (1.f - beta1) * gi;
-  const float vi = beta2 * v[i] + (1.f - beta2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  if (i < n) adam_update(p, part, ks, m, v, n, lr, st->step, i);
 }
 
 hipError_t launch_adam(float* p, const float* part, int ks, float* m, float* v, int64_t n,

@@ -360,20 +360,23 @@ int sur_gradients(game_surrogate_ctx* s, int n, const int32_t* skip, hipStream_t
     g.rowsum_part = bias_grad;
     g.part_ld = s->n_params;
     g.k_split = ks;
-    return launch_gemm(g, bf16, st);
+    return g;
   };
-  // dw3 = dy^T H2, db3 = sum dy
-  GAME_HIP(wgrad(gemm(s->dy, 0, 1, s->H2, 1, H, gp.w3, H, 1, H, n, nullptr, 0, nullptr, nullptr, 0,
-                      skip), gp.b3));
-  // dW2 = dZ2^T H1, db2 = column sums of dZ2
-  GAME_HIP(wgrad(gemm(s->dZ2, 1, H, s->H1, 1, H, gp.W2, H, H, H, n, nullptr, 0, nullptr, nullptr,
-                      0, skip), gp.b2));
+  // dw3 = dy^T H2, db3 = sum dy; dW2 = dZ2^T H1, db2 = column sums of dZ2
+  // (one launch: same operand layouts)
+  GAME_HIP(launch_gemm_pair(
+      wgrad(gemm(s->dy, 0, 1, s->H2, 1, H, gp.w3, H, 1, H, n, nullptr, 0, nullptr, nullptr, 0, skip),
+            gp.b3),
+      wgrad(gemm(s->dZ2, 1, H, s->H1, 1, H, gp.W2, H, H, H, n, nullptr, 0, nullptr, nullptr, 0,
+                 skip), gp.b2),
+      bf16, st));
   // dZ1 = (dZ2 W2) * gelu'(Z1)
   GAME_HIP(launch_gemm(gemm(s->dZ2, H, 1, p.W2, 1, H, s->dZ1, H, n, H, H, nullptr, 2, nullptr,
                             s->Z1, H, skip), bf16, st));
   // dW1 = dZ1^T X, db1 = column sums of dZ1
-  GAME_HIP(wgrad(gemm(s->dZ1, 1, H, s->Xb, 1, ni, gp.W1, ni, H, ni, n, nullptr, 0, nullptr, nullptr,
-                      0, skip), gp.b1));
+  GAME_HIP(launch_gemm(wgrad(gemm(s->dZ1, 1, H, s->Xb, 1, ni, gp.W1, ni, H, ni, n, nullptr, 0,
+                                  nullptr, nullptr, 0, skip), gp.b1),
+                       bf16, st));
   return GAME_OK;
 }
 
@@ -400,14 +403,21 @@ int enqueue_screening(game_ctx* h, hipStream_t s) {
   aa.st = sr->st;
   GAME_HIP(launch_archive_append(aa, s));
   GAME_HIP(launch_archive_stats(sr->arch_target, sr->st, h->state, P, c.archive, s));
-  for (int step = 0; step < c.train_steps; ++step) {
+  // Each Adam update shares its launch with the next step's minibatch draw.
+  if (c.train_steps > 0)
     GAME_HIP(launch_sample_minibatch(sr->arch_genes, sr->arch_target, K, sr->st, h->state, c.seed,
-                                     step, c.minibatch, sr->Xb, sr->tb, s));
+                                     0, c.minibatch, sr->Xb, sr->tb, s));
+  for (int step = 0; step < c.train_steps; ++step) {
     int ks = 1;
     int rc = sur_gradients(sr, c.minibatch, stop, s, true, &ks);
     if (rc) return rc;
-    GAME_HIP(launch_adam(sr->params, sr->kpart, ks, sr->m, sr->v, sr->n_params, c.lr, sr->st, stop,
-                         s));
+    if (step + 1 < c.train_steps)
+      GAME_HIP(launch_adam_sample(sr->params, sr->kpart, ks, sr->m, sr->v, sr->n_params, c.lr,
+                                  sr->st, stop, sr->arch_genes, sr->arch_target, K, h->state,
+                                  c.seed, step + 1, c.minibatch, sr->Xb, sr->tb, s));
+    else
+      GAME_HIP(launch_adam(sr->params, sr->kpart, ks, sr->m, sr->v, sr->n_params, c.lr, sr->st,
+                           stop, s));
   }
   const int C = c.oversample * (P - E);
   GAArgs ga = ga_args(&h->cfg, K);
