@@ -19,8 +19,9 @@
 //    copy costs no registers and one memory round trip.  When K does not
 //    fit, it passes through two buffers in chunks of whole feature pairs,
 //    the next chunk's copy in flight while the current one is used.
-//  * Accumulators start at zero; the epilogue adds the bias a_0(p), takes
-//    the residual against t_k, squares it (or applies the error function)
+//  * Accumulators start at zero.  A last K-step brings in the bias and the
+//    target (lane half 0: 1 x a_0(p); half 1: -t_k x 1), so the accumulators
+//    end at Out - t; the epilogue squares (or applies the error function)
 //    and sums the lane's 32 rows in float32, then adds into a float64
 //    running sum.
 //    Partials per (chromosome, split) are combined in a fixed order: the

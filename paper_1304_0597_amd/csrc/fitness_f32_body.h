@@ -155,11 +155,17 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
 
   for (int tile = tile_begin; tile < tile_end; ++tile) {
     const int64_t row0 = (int64_t)tile * kTileRows + wave * 64;
-    // One target per lane (the wave's 64 rows); the epilogue redistributes
-    // them across lanes, so the load's latency hides behind the K loop.
-    const float t_lane = global_f32(a.t)[row0 + lane < NP ? row0 + lane : NP - 1];
+    // Minus the targets of this lane's rows (0 past the data); they join
+    // with the bias in a last K-step, so the load's latency hides behind the
+    // K loop.
+    float nt[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      const int64_t r = row0 + rb * 32 + m;
+      nt[rb] = r < NP ? -global_f32(a.t)[r] : 0.f;
+    }
     // Accumulators start at zero (an inline constant, nothing to keep live
-    // across tiles); the bias joins in the epilogue.
+    // across tiles).
     f32x16 acc[2][2];
     acc[0][0] = f32x16{};
     acc[0][1] = f32x16{};
@@ -211,6 +217,17 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
       }
     }
 
+    // Bias and target K-step: lane half 0 multiplies 1 by a0 of its column,
+    // half 1 multiplies -t of its row by 1, so the accumulators end at
+    // Out - t.
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      const float ab = h ? nt[rb] : 1.f;
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ab, h ? 1.f : w0[cb], acc[rb][cb], 0, 0, 0);
+    }
+
     // Epilogue: residual Out - t, squared (or thresholded), summed over the
     // lane's 32 rows.  Accumulator register i of row block rb holds row
     // rb*32 + 8*(i/4) + 4*h + i%4 of the wave's 64 rows.
@@ -223,9 +240,8 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int rl = rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-          const float tv = __shfl(t_lane, rl);
-          float e0 = error_term<mode>((acc[rb][0][i] + w0[0]) - tv, a.R);
-          float e1 = error_term<mode>((acc[rb][1][i] + w0[1]) - tv, a.R);
+          float e0 = error_term<mode>(acc[rb][0][i], a.R);
+          float e1 = error_term<mode>(acc[rb][1][i], a.R);
           if (!full) {
             const bool ok = row0 + rl < NP;
             e0 = ok ? e0 : 0.f;
