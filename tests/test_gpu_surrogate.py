@@ -66,7 +66,7 @@ def test_init_matches_oracle(gg):
 
 @pytest.mark.parametrize("fp32", [True, False])
 @pytest.mark.parametrize("n_in,H,B", [(257, 256, 256), (29, 64, 100), (161, 32, 77), (40, 64, 1024),
-                                      (33, 96, 1100)])
+                                      (33, 96, 1100), (600, 48, 300)])
 def test_forward_and_gradients_match_oracle(gg, fp32, n_in, H, B):
     rng = np.random.default_rng(n_in + H + B)
     s = make(gg, n_in, fp32, H=H, minibatch=B, max_batch=B)
