@@ -211,14 +211,39 @@ def _run_to_target(gg, prob, precision, generations, target, surrogate=None):
     return res
 
 
+def _rho_trace(gg, prob, generations, surrogate):
+    """The audit's rank correlation and the screening count every 5
+    generations of the surrogate run (same seed, stepped one generation at a
+    time)."""
+    P = prob.population
+    cfg = gg.config(basis=prob.basis, degree=prob.degree, population=P,
+                    precision=gg.GAME_BF16, seed=0, max_generations=1 << 30, target=-1.0)
+    game = gg.Game(cfg, prob.X_dev, prob.t_dev)
+    sur = gg.Surrogate(gg.surrogate_config(**surrogate), prob.n_genes,
+                       surrogate["oversample"] * (P - cfg.elitism))
+    gg.game_attach_surrogate(game.h, sur.h)
+    game.init_population()
+    trace = []
+    for gen in range(generations):
+        game.step()
+        if gen % 5 == 4:
+            st = sur.stats()
+            trace.append({"generation": gen + 1, "rho": round(st["rho"], 3),
+                          "screened_total": st["screened_total"]})
+    sur.close()
+    game.close()
+    return trace
+
+
 def form_time_to_target(gg, prob, plain_generations=300, cap=3):
     """Time to a training-error target on the precision problem, same seed:
     plain FP32 GAME defines the target (its float64 best error after
     `plain_generations` generations); plain BF16 and the surrogate-screened
     BF16 form (network 257-256-256-1, 8x oversampled offspring, exact
     fallback below rank correlation 0.8) run until they reach it, at most
-    `cap` times as many generations.  Validation error of every final best
-    is reported beside it."""
+    `cap` times as many generations; the surrogate run's audit correlation
+    is traced, and an untrained, always-trusted network is run as the
+    ablation.  Validation error of every final best is reported beside it."""
     plain = _run_to_target(gg, prob, gg.GAME_FP32, plain_generations, 0.0)
     target = plain["train_mse_fp64"]
     plain["reached"] = True
@@ -226,11 +251,18 @@ def form_time_to_target(gg, prob, plain_generations=300, cap=3):
     sur_cfg = dict(hidden=256, fp32_operands=0, archive=16384, minibatch=1024, train_steps=24,
                    lr=1.5e-2, oversample=8, audit=64, rho_min=0.8, min_archive=4096, seed=0)
     chosen = _run_to_target(gg, prob, gg.GAME_BF16, cap * plain_generations, target, sur_cfg)
+    chosen["rho_trace"] = _rho_trace(gg, prob, chosen["generations"], sur_cfg)
+    # Ablation: the same screening with a network that is never trained and
+    # always trusted (offspring picked by random-weight predictions).
+    untrained_cfg = dict(sur_cfg, train_steps=0, rho_min=-1.0, min_archive=0)
+    untrained = _run_to_target(gg, prob, gg.GAME_BF16, cap * plain_generations, target,
+                               untrained_cfg)
     return {"workload": "precision problem (1,000,000 x 32, Chebyshev degree 8, population "
                         "4,096, validation 250,000 patterns), seed 0; target = plain FP32 best "
                         f"training error after {plain_generations} generations",
             "target_train_mse": target,
             "plain_fp32": plain, "plain_bf16": bf16, "surrogate_bf16": chosen,
+            "untrained_surrogate_bf16": untrained,
             "speedup_chosen_vs_plain": (plain["seconds"] / chosen["seconds"]
                                         if chosen["reached"] else None),
             "surrogate_config": sur_cfg}
