@@ -108,12 +108,17 @@ def test_forward_on_both_product_kernels(gg, fp32):
     params = [np.asarray(x, np.float64) for x in split(flat, n_in, H)]
     X = rng.uniform(-1, 1, (4141, n_in)).astype(np.float32)
     y_ref, _ = mlp.forward(params, X)
+    ys = {}
     for n in (4096, 4141):
         y = s.predict(torch.from_numpy(X[:n]).cuda()).cpu().numpy()
         if fp32:
             assert rel_l2(y, y_ref[:n]) < 1e-5, n
         else:
             assert rel_l2(y, y_ref[:n]) < 2e-2 and cosine(y, y_ref[:n]) > 0.999, n
+        ys[n] = y
+    # both kernels follow the same range arithmetic: a row's prediction does
+    # not depend on the batch it is scored in
+    assert np.array_equal(ys[4096], ys[4141][:4096])
     s.close()
 
 
