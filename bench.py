@@ -100,6 +100,26 @@ def cpu_baseline(prob, P, seconds=10.0):
                       f"of {P} chromosomes"}
 
 
+def cpu_serial(prob, seconds=5.0):
+    """The oracle's plain serial C fitness (one thread, one term at a time:
+    the counterpart of the paper's serial version) on chromosomes of the
+    workload over every pattern, for about `seconds`; evals/s."""
+    from oracle import serial
+    rng = np.random.default_rng(2)
+    W = rng.uniform(-1, 1, (1, prob.n_genes)).astype(np.float32)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        serial.fitness(prob.X, prob.t, W, prob.basis, prob.degree)
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    return {"value": n * prob.n_patterns / el, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} chromosomes x {prob.n_patterns} patterns, serial C float64 "
+                      f"({el / n:.2f} s each)"}
+
+
 def time_fitness(gg, game, genes, n, reps, stream):
     """Average duration (s) of one fitness launch (+ its finish kernel) on
     the library's stream, timed with HIP events."""
@@ -509,6 +529,10 @@ def main():
     if not args.no_cpu:
         log("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(prob, P)
+        log("serial oracle on one host core")
+        ser = cpu_serial(prob)
+        ser["gpu_over_this"] = out["value"] / ser["value"]
+        out["cpu_serial"] = ser
     print(json.dumps(out), flush=True)
 
 
