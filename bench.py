@@ -528,11 +528,12 @@ def main():
         del pprob
     if not args.no_cpu:
         log("oracle on the host cores")
-        out["cpu_baseline"] = cpu_baseline(prob, P)
+        base = cpu_baseline(prob, P)
         log("serial oracle on one host core")
         ser = cpu_serial(prob)
         ser["gpu_over_this"] = out["value"] / ser["value"]
-        out["cpu_serial"] = ser
+        base["serial"] = ser
+        out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
 
 
