@@ -220,8 +220,12 @@ def _run_to_target(gg, prob, precision, generations, target, surrogate=None, see
     best_dev = torch.from_numpy(best).to(dev).view(1, -1)
     train64 = float(game.rescore64(best_dev)[0])
     val64 = float(game.rescore64(best_dev, prob.Xv_dev, prob.tv_dev)[0])
+    # exact evaluations: the population each generation, plus the audited
+    # children when a surrogate screens
+    per_gen = P + (surrogate["audit"] if surrogate is not None else 0)
     res = {"generations": gens, "seconds": elapsed, "reached": bool(train64 <= target * (1 + 1e-3)),
            "train_mse_fp64": train64, "validation_mse_fp64": val64,
+           "exact_evaluations": int(gens) * per_gen,
            "ms_per_generation": elapsed * 1e3 / max(gens, 1)}
     if sur is not None:
         st = sur.stats()

@@ -295,7 +295,9 @@ int64_t game_surrogate_num_params(game_surrogate_t s);
 int game_surrogate_get_params(game_surrogate_t s, float* params_dev);
 int game_surrogate_set_params(game_surrogate_t s, const float* params_dev);
 
-/* Predictions y_dev [n] for genes_dev [n x n_genes], 1 <= n <= max_batch. */
+/* Predictions y_dev [n] for genes_dev [n x n_genes], 1 <= n <= max_batch.
+ * A row's prediction does not depend on n or on the other rows: every
+ * product sums in one fixed order whatever the batch size. */
 int game_surrogate_predict(game_surrogate_t s, const float* genes_dev, int32_t n, float* y_dev);
 
 /* Gradients grads_dev [num_params] of mean((y - target)^2) over n rows
