@@ -1,6 +1,6 @@
 """Fitness-surrogate network in float64: a multilayer perceptron with GELU
 hidden layers, its loss, analytic gradients, Adam update, parameter
-initialisation and the Spearman rank correlation used to judge it.
+initialisation and the Spearman rank correlation used to assess it.
 
 Test infrastructure (see ``oracle/__init__.py``).  The network maps a
 chromosome's genes to a standardised log error:
