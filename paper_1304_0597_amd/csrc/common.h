@@ -304,9 +304,8 @@ inline int gemm_k_split(int K) {
   return r < 1 ? 1 : (r > 8 ? 8 : r);
 }
 hipError_t launch_gemm(const GemmArgs& g, bool bf16, hipStream_t s);
-// Two independent small products with the same operand layouts and k_split
-// in one launch.
-hipError_t launch_gemm_pair(const GemmArgs& a, const GemmArgs& b, bool bf16, hipStream_t s);
+// Up to 3 independent minibatch-sized products in one launch.
+hipError_t launch_gemm_multi(const GemmArgs* gs, int n, bool bf16, hipStream_t s);
 // Output layer (and with t set, its backward); see out_layer_kernel.
 hipError_t launch_out_layer(const float* H2, const float* w3, const float* b3, int B, int H,
                             float* y, const float* t, const float* Z2, float* dy, float* dZ2,

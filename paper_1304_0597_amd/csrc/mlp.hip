@@ -266,24 +266,20 @@ size_t small_lds_bytes(const GemmArgs& g) {
   return ((size_t)kSmallWaves * 64 + (stage > red ? stage : red)) * sizeof(float);
 }
 
-// One launch may carry two independent products of the same operand
-// layouts (row tiles [0, ty0) serve g[0], the rest g[1]).
-struct GemmPair {
-  GemmArgs g[2];
-  int32_t ty0;
+// One launch may carry up to kMaxProducts independent products (row tiles
+// [ty_end[p-1], ty_end[p]) serve product p); each product's workgroups take
+// the operand-layout variant of its own operands.
+constexpr int kMaxProducts = 3;
+struct GemmMulti {
+  GemmArgs g[kMaxProducts];
+  int32_t ty_end[kMaxProducts];
+  int32_t n;
 };
 
 template <bool BF16, bool SA, bool SB>
-__global__ __launch_bounds__(64 * kSmallWaves) __attribute__((amdgpu_waves_per_eu(1, 2)))
-void gemm_small_kernel(GemmPair gp) {
-  extern __shared__ float small_lds[];
+__device__ __forceinline__ void small_body(const GemmArgs& g, int by, float* small_lds) {
   float* red_rs = small_lds;                            // [waves][64]
   float* red = small_lds + kSmallWaves * 64;            // [waves][32 * 32], over the staging areas
-  const int pi = (int)blockIdx.y >= gp.ty0 ? 1 : 0;
-  const GemmArgs& g = gp.g[pi];
-  const int by = (int)blockIdx.y - (pi ? gp.ty0 : 0);
-  if (g.skip && *g.skip) return;
-  if ((int)blockIdx.x * 32 >= g.N || by * 32 >= g.M) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int r = lane & 31, h = lane >> 5;
@@ -357,6 +353,26 @@ void gemm_small_kernel(GemmPair gp) {
 }
 
 template <bool BF16>
+__global__ __launch_bounds__(64 * kSmallWaves) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void gemm_small_kernel(GemmMulti gm) {
+  extern __shared__ float small_lds[];
+  int pi = 0;
+  while (pi + 1 < gm.n && (int)blockIdx.y >= gm.ty_end[pi]) ++pi;
+  const GemmArgs& g = gm.g[pi];
+  const int by = (int)blockIdx.y - (pi ? gm.ty_end[pi - 1] : 0);
+  if (g.skip && *g.skip) return;
+  if ((int)blockIdx.x * 32 >= g.N || by * 32 >= g.M || (int)blockIdx.z >= g.k_split) return;
+  const bool sa = small_staged(g.lda_m, g.lda_k, g.M), sb = small_staged(g.ldb_n, g.ldb_k, g.N);
+  if (sa) {
+    if (sb) small_body<BF16, true, true>(g, by, small_lds);
+    else small_body<BF16, true, false>(g, by, small_lds);
+  } else {
+    if (sb) small_body<BF16, false, true>(g, by, small_lds);
+    else small_body<BF16, false, false>(g, by, small_lds);
+  }
+}
+
+template <bool BF16>
 static hipError_t launch_gemm_t(const GemmArgs& g, const dim3& grid, hipStream_t s) {
   static bool lds_set = false;   // one attribute call per instantiation
   if (!lds_set) {
@@ -370,27 +386,18 @@ static hipError_t launch_gemm_t(const GemmArgs& g, const dim3& grid, hipStream_t
   return hipGetLastError();
 }
 
-template <bool BF16, bool SA, bool SB>
-static hipError_t launch_small_sab(const GemmPair& g, const dim3& grid, size_t lds, hipStream_t s) {
+template <bool BF16>
+static hipError_t launch_small_t(const GemmMulti& gm, const dim3& grid, size_t lds, hipStream_t s) {
   static bool lds_set = false;   // one attribute call per instantiation
   if (!lds_set) {
     const int most = (int)((kSmallWaves * 64 + kSmallWaves * 2 * kStageFloats) * sizeof(float));
-    const hipError_t e = hipFuncSetAttribute((const void*)gemm_small_kernel<BF16, SA, SB>,
+    const hipError_t e = hipFuncSetAttribute((const void*)gemm_small_kernel<BF16>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, most);
     if (e != hipSuccess) return e;
     lds_set = true;
   }
-  hipLaunchKernelGGL((gemm_small_kernel<BF16, SA, SB>), grid, dim3(64 * kSmallWaves), lds, s, g);
+  hipLaunchKernelGGL(gemm_small_kernel<BF16>, grid, dim3(64 * kSmallWaves), lds, s, gm);
   return hipGetLastError();
-}
-
-template <bool BF16>
-static hipError_t launch_small_t(const GemmPair& g, bool sa, bool sb, const dim3& grid, size_t lds,
-                                 hipStream_t s) {
-  if (sa) return sb ? launch_small_sab<BF16, true, true>(g, grid, lds, s)
-                    : launch_small_sab<BF16, true, false>(g, grid, lds, s);
-  return sb ? launch_small_sab<BF16, false, true>(g, grid, lds, s)
-            : launch_small_sab<BF16, false, false>(g, grid, lds, s);
 }
 
 // Checks a product's arguments; small: it runs on gemm_small_kernel.
@@ -410,43 +417,37 @@ static hipError_t check_gemm(GemmArgs& g, bool* small) {
   return hipSuccess;
 }
 
+hipError_t launch_gemm_multi(const GemmArgs* gs, int n, bool bf16, hipStream_t s) {
+  if (n < 1 || n > kMaxProducts) return hipErrorInvalidValue;
+  GemmMulti gm{};
+  gm.n = n;
+  int tx = 0, ty = 0, tz = 1;
+  size_t lds = 0;
+  for (int p = 0; p < n; ++p) {
+    GemmArgs g = gs[p];
+    bool small = false;
+    const hipError_t e = check_gemm(g, &small);
+    if (e != hipSuccess) return e;
+    if (!small) return hipErrorInvalidValue;
+    gm.g[p] = g;
+    tx = std::max(tx, (g.N + 31) / 32);
+    ty += (g.M + 31) / 32;
+    gm.ty_end[p] = ty;
+    tz = std::max(tz, g.k_split);
+    lds = std::max(lds, small_lds_bytes(g));
+  }
+  const dim3 grid(tx, ty, tz);
+  return bf16 ? launch_small_t<true>(gm, grid, lds, s) : launch_small_t<false>(gm, grid, lds, s);
+}
+
 hipError_t launch_gemm(const GemmArgs& g0, bool bf16, hipStream_t s) {
   GemmArgs g = g0;
   bool small = false;
   const hipError_t e = check_gemm(g, &small);
   if (e != hipSuccess) return e;
-  if (small) {
-    GemmPair gp{};
-    gp.g[0] = g;
-    gp.g[1] = g;
-    gp.ty0 = (g.M + 31) / 32;
-    const dim3 grid((g.N + 31) / 32, gp.ty0, g.k_split);
-    const bool sa = small_staged(g.lda_m, g.lda_k, g.M), sb = small_staged(g.ldb_n, g.ldb_k, g.N);
-    return bf16 ? launch_small_t<true>(gp, sa, sb, grid, small_lds_bytes(g), s)
-                : launch_small_t<false>(gp, sa, sb, grid, small_lds_bytes(g), s);
-  }
+  if (small) return launch_gemm_multi(&g, 1, bf16, s);
   const dim3 grid((g.N + kGemmTile - 1) / kGemmTile, (g.M + kGemmTile - 1) / kGemmTile, 1);
   return bf16 ? launch_gemm_t<true>(g, grid, s) : launch_gemm_t<false>(g, grid, s);
-}
-
-hipError_t launch_gemm_pair(const GemmArgs& a0, const GemmArgs& b0, bool bf16, hipStream_t s) {
-  GemmArgs a = a0, b = b0;
-  bool sm_a = false, sm_b = false;
-  hipError_t e = check_gemm(a, &sm_a);
-  if (e == hipSuccess) e = check_gemm(b, &sm_b);
-  if (e != hipSuccess) return e;
-  const bool sa = small_staged(a.lda_m, a.lda_k, a.M), sb = small_staged(a.ldb_n, a.ldb_k, a.N);
-  if (!sm_a || !sm_b || a.k_split != b.k_split || sa != small_staged(b.lda_m, b.lda_k, b.M) ||
-      sb != small_staged(b.ldb_n, b.ldb_k, b.N))
-    return hipErrorInvalidValue;
-  GemmPair gp{};
-  gp.g[0] = a;
-  gp.g[1] = b;
-  gp.ty0 = (a.M + 31) / 32;
-  const dim3 grid((std::max(a.N, b.N) + 31) / 32, gp.ty0 + (b.M + 31) / 32, a.k_split);
-  const size_t lds = std::max(small_lds_bytes(a), small_lds_bytes(b));
-  return bf16 ? launch_small_t<true>(gp, sa, sb, grid, lds, s)
-              : launch_small_t<false>(gp, sa, sb, grid, lds, s);
 }
 
 // Output layer, one wave per row b: y_b = b3 + sum_j H2[b][j] w3[j] in

@@ -362,17 +362,15 @@ int sur_gradients(game_surrogate_ctx* s, int n, const int32_t* skip, hipStream_t
     g.k_split = ks;
     return g;
   };
-  // dw3 = dy^T H2, db3 = sum dy; dW2 = dZ2^T H1, db2 = column sums of dZ2
-  // (one launch: same operand layouts)
-  GAME_HIP(launch_gemm_pair(
-      wgrad(gemm(s->dy, 0, 1, s->H2, 1, H, gp.w3, H, 1, H, n, nullptr, 0, nullptr, nullptr, 0, skip),
-            gp.b3),
+  // One launch: dw3 = dy^T H2 and db3 = sum dy; dW2 = dZ2^T H1 and db2 =
+  // column sums of dZ2; dZ1 = (dZ2 W2) * gelu'(Z1).
+  const GemmArgs prods[3] = {
+      wgrad(gemm(s->dy, 0, 1, s->H2, 1, H, gp.w3, H, 1, H, n, nullptr, 0, nullptr, nullptr, 0,
+                 skip), gp.b3),
       wgrad(gemm(s->dZ2, 1, H, s->H1, 1, H, gp.W2, H, H, H, n, nullptr, 0, nullptr, nullptr, 0,
                  skip), gp.b2),
-      bf16, st));
-  // dZ1 = (dZ2 W2) * gelu'(Z1)
-  GAME_HIP(launch_gemm(gemm(s->dZ2, H, 1, p.W2, 1, H, s->dZ1, H, n, H, H, nullptr, 2, nullptr,
-                            s->Z1, H, skip), bf16, st));
+      gemm(s->dZ2, H, 1, p.W2, 1, H, s->dZ1, H, n, H, H, nullptr, 2, nullptr, s->Z1, H, skip)};
+  GAME_HIP(launch_gemm_multi(prods, 3, bf16, st));
   // dW1 = dZ1^T X, db1 = column sums of dZ1
   GAME_HIP(launch_gemm(wgrad(gemm(s->dZ1, 1, H, s->Xb, 1, ni, gp.W1, ni, H, ni, n, nullptr, 0,
                                   nullptr, nullptr, 0, skip), gp.b1),
