@@ -467,6 +467,34 @@ __global__ __launch_bounds__(256) void out_layer_kernel(const float* H2, const f
   const int lane = threadIdx.x & 63;
   if (b >= B) return;
   const float* h = H2 + (int64_t)b * H;
+  constexpr int kRow = 8;   // up to 512 units: the row's values stay in registers
+  if (H <= 64 * kRow) {
+    // Every load (H2, w3, Z2, t) issued before the first use: one memory
+    // round trip; the sums keep the order of the general path below.
+    float hv[kRow], wv[kRow], zv[kRow];
+#pragma unroll
+    for (int u = 0; u < kRow; ++u) {
+      const int j = min(lane + 64 * u, H - 1);
+      hv[u] = h[j];
+      wv[u] = w3[j];
+      zv[u] = t ? Z2[(int64_t)b * H + j] : 0.f;
+    }
+    const float tb = t ? t[b] : 0.f;
+    float acc = 0.f;
+#pragma unroll
+    for (int u = 0; u < kRow; ++u)
+      if (lane + 64 * u < H) acc = fmaf(hv[u], wv[u], acc);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    const float yb = acc + b3[0];
+    if (lane == 0) y[b] = yb;
+    if (!t) return;
+    const float d = 2.f * (yb - tb) / (float)B;
+    if (lane == 0) dy[b] = d;
+#pragma unroll
+    for (int u = 0; u < kRow; ++u)
+      if (lane + 64 * u < H) dZ2[(int64_t)b * H + lane + 64 * u] = d * wv[u] * gelu_grad_f(zv[u]);
+    return;
+  }
   float acc = 0.f;
   for (int j = lane; j < H; j += 64) acc = fmaf(h[j], w3[j], acc);
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
