@@ -165,3 +165,32 @@ def test_batched_workload_sample(gg):
         ref = og.fitness(p.X, p.t, before[k][idx], p.basis, p.degree)
         assert np.all(np.abs(fit[idx] - ref) <= 1e-5 * ref + 1e-7 * np.mean(p.t.astype(np.float64) ** 2))
     b.close()
+
+
+def test_batch_error_functions_follow_single_runs(gg):
+    """Runs with RMSE, TMSE (|r| > R) and the literal TMSE (r^2 > R) in one
+    batch: each follows its single-run trajectory bit for bit."""
+    runs = [(900, 6, 3, 40, 0), (1300, 9, 5, 70, 2), (700, 4, 8, 33, 1)]
+    problems, cfgs = [], []
+    for i, (NP, N, d, P, basis) in enumerate(runs):
+        rng = np.random.default_rng(40 + i)
+        X = rng.uniform(-1, 1, (NP, N)).astype(np.float32)
+        t = (rng.random(NP) < 0.5).astype(np.float32)
+        problems.append((torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda()))
+        cfgs.append(gg.config(basis=basis, degree=d, population=P, seed=7 + i, elitism=2,
+                              error_fn=i + 1, tmse_R=0.49, max_generations=5, target=0.0))
+    b = gg.Batch(problems, cfgs)
+    b.init()
+    gens, best = b.run()
+    assert np.all(gens == 5)
+    for r, c in enumerate(cfgs):
+        g = gg.Game(c, *problems[r])
+        g.init_population()
+        n, _, err = g.run()
+        assert n == 5
+        pb, fb = b.population(r)
+        ps, fs = g.population()
+        assert np.array_equal(bits(pb.cpu().numpy()), bits(ps.cpu().numpy())), r
+        assert abs(best[r] - err) <= 1e-12 * max(err, 1e-30), r
+        g.close()
+    b.close()
