@@ -232,10 +232,19 @@ hipError_t launch_finish_rank(const RankArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// reset 1: start at generation `gen`; 0: new limits only; 2: new limits,
+// and a run stopped on its last evaluation continues from it: the stop flag
+// clears and the generation counter advances, as the stop test does when no
+// criterion holds (the caller has checked that none does).
 __global__ void set_state_kernel(RunState* st, int32_t gen, int32_t max_gen, double target,
                                  int32_t reset) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (reset) {
+  if (reset == 2) {
+    st->stop = 0;
+    st->stop_seen = 0;
+    st->gen = st->gen + 1;
+  }
+  if (reset == 1) {
     st->gen = gen;
     st->stop = 0;
     st->stop_seen = 0;
@@ -262,11 +271,33 @@ __device__ __forceinline__ float fit_at(const float* fit, int i) {
   return rank_key_value(fit[i]);
 }
 
-__device__ __forceinline__ int tournament(const float* fit, const uint32_t* w, int k, int P) {
-  int best = (int)(((uint64_t)w[0] * (uint64_t)P) >> 32);
+// The stream-1 words of one child pair, produced in order: word i is the
+// low (i even) or high (i odd) half of o[(i % 8) / 2] of block i / 8.  Words
+// are read in increasing order, so each block is drawn once and only the
+// current block is held (wave-uniform registers, no per-lane array).
+struct PairWords {
+  uint64_t seed, gen, unit;
+  int blk;
+  U64x4 r;
+  __device__ PairWords(uint64_t s, uint64_t g, uint64_t u) : seed(s), gen(g), unit(u), blk(-1) {}
+  __device__ uint32_t operator()(int i) {
+    const int b = i >> 3;
+    if (b != blk) {
+      r = draw(seed, 1, gen, unit, (uint64_t)b);
+      blk = b;
+    }
+    const int o = (i & 7) >> 1;
+    const uint64_t v = o == 0 ? r.o0 : (o == 1 ? r.o1 : (o == 2 ? r.o2 : r.o3));
+    return (i & 1) ? (uint32_t)(v >> 32) : (uint32_t)v;
+  }
+};
+
+// Tournament of k draws, words [w0, w0 + k) of the pair.
+__device__ __forceinline__ int tournament(const float* fit, PairWords& w, int w0, int k, int P) {
+  int best = (int)(((uint64_t)w(w0) * (uint64_t)P) >> 32);
   float fb = fit_at(fit, best);
   for (int c = 1; c < k; ++c) {
-    const int cand = (int)(((uint64_t)w[c] * (uint64_t)P) >> 32);
+    const int cand = (int)(((uint64_t)w(w0 + c) * (uint64_t)P) >> 32);
     const float fc = fit_at(fit, cand);
     if (fc < fb || (fc == fb && cand < best)) {
       best = cand;
@@ -275,8 +306,6 @@ __device__ __forceinline__ int tournament(const float* fit, const uint32_t* w, i
   }
   return best;
 }
-
-constexpr int kMaxTournament = 64;
 
 // Linear ranking, pressure 2: rank r has weight P - r; the integer draw
 // t = (u32 * P(P+1)/2) >> 32 falls in rank r's cumulative interval.
@@ -343,15 +372,25 @@ hipError_t launch_roulette_cum(const float* fit, int32_t P, double* cum, const i
 
 // Body of one wave: output group `wid` (an elite slot, or child pair
 // wid - E) of the run described by `a`.
-__device__ void ga_next_wave(const GAArgs& a, int wid) {
+// Pointer c ? x : y as integer arithmetic on already loaded values.  (A
+// select between two fields of the argument structure is otherwise turned
+// into a load through a selected field address, which keeps the whole
+// structure in private memory.)
+template <class T>
+__device__ __forceinline__ T* pick(bool c, T* x, T* y) {
+  const uintptr_t ux = (uintptr_t)x, uy = (uintptr_t)y;
+  return (T*)(uy ^ ((ux ^ uy) & (uintptr_t)(-(intptr_t)c)));
+}
+
+__device__ __forceinline__ void ga_next_wave(const GAArgs& a, int wid) {
   if (a.stop && *a.stop) return;
   int gen;
   const float* __restrict__ pop;
   float* __restrict__ out;
   if (a.gen_ptr) {
     gen = *a.gen_ptr;
-    pop = ((gen - 1) & 1) ? a.pop_b : a.pop_a;
-    out = (gen & 1) ? a.out_b : a.out_a;
+    pop = pick(((gen - 1) & 1) != 0, a.pop_b, a.pop_a);
+    out = pick((gen & 1) != 0, a.out_b, a.out_a);
   } else {
     gen = a.generation;
     pop = a.pop_a;
@@ -369,37 +408,31 @@ __device__ void ga_next_wave(const GAArgs& a, int wid) {
   const int q = wid - E;
   if (q >= n_pairs) return;
 
-  // selection words for pair q
-  uint32_t w[2 * kMaxTournament + 2];
+  // Selection words of pair q, consumed in order: parent 1, parent 2 (k
+  // words each for a tournament, one for ranking or roulette), the
+  // crossover coin, the cut point.
+  PairWords w(a.seed, (uint64_t)gen, (uint64_t)q);
   const int k = a.selection == 0 ? a.k : 1;
-  const int n_words = 2 * k + 2;
-  for (int b = 0; b * 8 < n_words; ++b) {
-    const U64x4 r = draw(a.seed, 1, (uint64_t)gen, (uint64_t)q, (uint64_t)b);
-    const uint64_t o[4] = {r.o0, r.o1, r.o2, r.o3};
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int idx = b * 8 + i;
-      if (idx < n_words) w[idx] = (i & 1) ? (uint32_t)(o[i >> 1] >> 32) : (uint32_t)o[i >> 1];
-    }
-  }
   int p1, p2;
   if (a.selection == 1) {
-    p1 = ranking_pick(a.order, P, w[0]);
-    p2 = ranking_pick(a.order, P, w[1]);
+    p1 = ranking_pick(a.order, P, w(0));
+    p2 = ranking_pick(a.order, P, w(1));
   } else if (a.selection == 2) {
-    p1 = roulette_pick(a.cum, P, w[0]);
-    p2 = roulette_pick(a.cum, P, w[1]);
+    p1 = roulette_pick(a.cum, P, w(0));
+    p2 = roulette_pick(a.cum, P, w(1));
   } else {
-    p1 = tournament(a.fitness, w, k, P);
-    p2 = tournament(a.fitness, w + k, k, P);
+    p1 = tournament(a.fitness, w, 0, k, P);
+    p2 = tournament(a.fitness, w, k, k, P);
   }
-  const bool cross = (uint64_t)w[2 * k] < a.thr_cross;
-  const int cut = 1 + (int)(((uint64_t)w[2 * k + 1] * (uint64_t)(K - 1)) >> 32);
+  const bool cross = (uint64_t)w(2 * k) < a.thr_cross;
+  const int cut = 1 + (int)(((uint64_t)w(2 * k + 1) * (uint64_t)(K - 1)) >> 32);
 
   const int sa = E + 2 * q, sb = sa + 1;
   const bool has_b = sb < n_slots;
-  float* __restrict__ out_a = a.children ? a.children + (int64_t)(sa - E) * K : out + (int64_t)sa * K;
-  float* __restrict__ out_b = a.children ? a.children + (int64_t)(sb - E) * K : out + (int64_t)sb * K;
+  float* __restrict__ out_a = pick(a.children != nullptr, a.children + (int64_t)(sa - E) * K,
+                                   out + (int64_t)sa * K);
+  float* __restrict__ out_b = pick(a.children != nullptr, a.children + (int64_t)(sb - E) * K,
+                                   out + (int64_t)sb * K);
   for (int g = lane; g < K; g += 64) {
     const float x1 = pop[(int64_t)p1 * K + g];
     const float x2 = pop[(int64_t)p2 * K + g];
@@ -580,8 +613,11 @@ hipError_t launch_mlp_init(float* params, int n_in, int H, uint64_t seed, hipStr
 // Appends the generation just evaluated (genes and log error, the error
 // clamped to [1e-30, 1e30]) at the archive's ring position.  Skipped when
 // the generation's fitness launch did not run (the run had stopped).
+// A generation that stopped the run is not archived: a run resumed later
+// evaluates that population again and archives it then, as one uninterrupted
+// run would.
 __global__ void archive_append_kernel(ArchiveArgs a) {
-  if (a.run->stop_seen) return;
+  if (a.run->stop) return;
   const int ev = a.run->evaluated;
   const float* pop = (ev & 1) ? a.pop1 : a.pop0;
   const int head = a.st->head;
@@ -614,7 +650,7 @@ __global__ __launch_bounds__(1024) void archive_stats_kernel(const float* target
                                                              int capacity) {
   __shared__ double s1[1024], s2[1024];
   __shared__ int cnt;
-  if (run->stop_seen) return;
+  if (run->stop) return;
   if (threadIdx.x == 0) {
     const int c = min(st->count + P, capacity);
     st->count = c;

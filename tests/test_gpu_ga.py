@@ -69,6 +69,9 @@ GA_CASES = [
     (40, 700, 4, 5, 1, 0.0, 0.0, 0.1),
     (40, 13, 40, 1, 0, 1.0, 0.0, 0.1),
     (9, 17, 64 // 8, 3, 1, 0.5, 0.5, 0.7),
+    # tournaments longer than one Philox block of words, up to k = P
+    (200, 31, 100, 2, 0, 0.9, 0.05, 0.1),
+    (70, 9, 70, 1, 1, 1.0, 0.5, 0.3),
 ]
 
 
@@ -187,6 +190,52 @@ def test_resume_is_bit_exact(gg):
     assert np.array_equal(bits(pop_res.cpu().numpy()), bits(pop_full.cpu().numpy()))
     for g in (g1, g2, g3):
         g.close()
+
+
+def test_run_resumes_when_limits_are_raised(gg):
+    """A run stopped by its generation limit continues, under a higher
+    limit, exactly as one uninterrupted run: run(10) then run(20) ends where
+    run(20) ends, bit for bit; a second call whose limits still hold does
+    nothing."""
+    _, _, g1 = _small_game(gg)
+    g1.init_population()
+    gens1, best1, err1 = g1.run(max_generations=20, target=0.0)
+    _, _, g2 = _small_game(gg)
+    g2.init_population()
+    assert g2.run(max_generations=10, target=0.0)[0] == 10
+    assert g2.run(max_generations=10, target=0.0)[0] == 10          # still stopped
+    assert g2.state()["stopped"] == 1
+    gens2, best2, err2 = g2.run(max_generations=20, target=0.0)
+    assert gens1 == gens2 == 20 and err1 == err2
+    assert np.array_equal(bits(best1), bits(best2))
+    for a, b in zip(g1.population(), g2.population()):
+        assert np.array_equal(bits(a.cpu().numpy()), bits(b.cpu().numpy()))
+    # a target that the stopped run's best already meets: nothing runs
+    gens3, _, err3 = g2.run(max_generations=40, target=err2 * 2)
+    assert gens3 == 20 and err3 == err2
+    g1.close()
+    g2.close()
+
+
+def test_run_stops_queuing_after_an_early_stop(gg):
+    """A target reached long before the generation limit: the run stops at
+    the same generation as single steps do, and a very large limit does not
+    make game_run queue work for every remaining generation (it returns in
+    well under the time that would take)."""
+    import time
+    _, _, g1 = _small_game(gg)
+    g1.init_population()
+    g1.run(max_generations=30, target=0.0)
+    target = g1.state()["best_error"]
+    _, _, g2 = _small_game(gg)
+    g2.init_population()
+    t0 = time.perf_counter()
+    gens, _, err = g2.run(max_generations=(1 << 31) - 1, target=target)
+    elapsed = time.perf_counter() - t0
+    assert gens <= 30 and err <= target
+    assert elapsed < 20.0
+    g1.close()
+    g2.close()
 
 
 SELECTION_CASES = [
