@@ -21,24 +21,35 @@ namespace game {
 
 namespace {
 
-// The single-run float32 body for one item, at a compile-time degree; kept
-// out of line so each degree gets its own register allocation.
-template <int BASIS, int D>
-__device__ __attribute__((noinline)) void item_body(const FitArgs& fa, const float* genes, int split, int ctile, float* lds) {
-  fitness_f32_block<BASIS, D>(fa, genes, split, ctile, lds);
-}
-
-template <int BASIS>
-__device__ void item_degree(int degree, const FitArgs& fa, const float* genes, int split,
-                            int ctile, float* lds) {
-  switch (degree) {
-#define GAME_CASE(D) case D: item_body<BASIS, D>(fa, genes, split, ctile, lds); break;
-    GAME_CASE(1) GAME_CASE(2) GAME_CASE(3) GAME_CASE(4) GAME_CASE(5) GAME_CASE(6)
-    GAME_CASE(7) GAME_CASE(8) GAME_CASE(9) GAME_CASE(10) GAME_CASE(11) GAME_CASE(12)
-    GAME_CASE(13) GAME_CASE(14) GAME_CASE(15) GAME_CASE(16)
-#undef GAME_CASE
-    default: break;
-  }
+// The single-run float32 body for one item of run `run`, with the run's
+// expansion family and degree read at run time: one body serves every run,
+// so the kernel makes no calls (a call per item would save and restore the
+// callee's registers in private memory every time) and has the register
+// allocation of one body.
+__device__ __forceinline__ void item_body(const BatchRun* __restrict__ run, const float* genes,
+                                          int split, int ctile, float* lds) {
+  FitArgs fa{};
+  fa.X = run->X;
+  fa.t = run->t;
+  fa.partial = run->partial;
+  fa.NP = run->NP;
+  fa.N = run->N;
+  fa.K = run->K;
+  fa.n_chrom = run->P;
+  fa.U = run->U;
+  fa.Q = run->Q;
+  fa.pairs_per_chunk = run->pairs_per_chunk;
+  fa.n_chunks = run->n_chunks;
+  fa.n_ctiles = run->n_ctiles;
+  fa.ld_partial = run->ld_partial;
+  fa.n_splits = run->n_splits;
+  fa.tiles_per_split = run->tiles_per_split;
+  fa.n_tiles = run->n_tiles;
+  fa.error_fn = run->error_fn;
+  fa.R = run->R;
+  fa.degree = run->D;
+  fa.basis = run->basis;
+  fitness_f32_block<-1, 0>(fa, genes, split, ctile, lds);
 }
 
 }  // namespace
@@ -67,36 +78,12 @@ __global__ __launch_bounds__(kFitThreads, 2) void fitness_batch_kernel(BatchArgs
     const int it = item_sh;
     if (it < 0) break;
     const BatchItem w = a.items[it];
-    const BatchRun& run = a.runs[w.run];
-    const int stopped = run.state->stop;
-    if (w.ctile == 0 && w.split == 0 && threadIdx.x == 0) run.state->stop_seen = stopped;
+    const BatchRun* run = a.runs + w.run;
+    const int stopped = run->state->stop;
+    if (w.ctile == 0 && w.split == 0 && threadIdx.x == 0) run->state->stop_seen = stopped;
     if (stopped) continue;
-    FitArgs fa{};
-    fa.X = run.X;
-    fa.t = run.t;
-    fa.partial = run.partial;
-    fa.NP = run.NP;
-    fa.N = run.N;
-    fa.K = run.K;
-    fa.n_chrom = run.P;
-    fa.U = run.U;
-    fa.Q = run.Q;
-    fa.pairs_per_chunk = run.pairs_per_chunk;
-    fa.n_chunks = run.n_chunks;
-    fa.n_ctiles = run.n_ctiles;
-    fa.ld_partial = run.ld_partial;
-    fa.n_splits = run.n_splits;
-    fa.tiles_per_split = run.tiles_per_split;
-    fa.n_tiles = run.n_tiles;
-    fa.error_fn = run.error_fn;
-    fa.R = run.R;
-    const float* genes = (run.state->gen & 1) ? run.pop1 : run.pop0;
-    switch (run.basis) {
-      case 0: item_degree<0>(run.D, fa, genes, w.split, w.ctile, lds); break;
-      case 1: item_degree<1>(run.D, fa, genes, w.split, w.ctile, lds); break;
-      case 2: item_degree<2>(run.D, fa, genes, w.split, w.ctile, lds); break;
-      default: item_degree<3>(run.D, fa, genes, w.split, w.ctile, lds); break;
-    }
+    const float* genes = (run->state->gen & 1) ? run->pop1 : run->pop0;
+    item_body(run, genes, w.split, w.ctile, lds);
   }
 }
 

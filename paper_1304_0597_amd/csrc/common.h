@@ -94,6 +94,8 @@ struct FitArgs {
   int32_t xcd_remap;
   int32_t error_fn;
   float R;
+  int32_t degree;           // d, read by the run-time-degree body only
+  int32_t basis;            // expansion family, read by the run-time-family body only
 };
 
 // Grid/chunk planning shared by every fitness launch.

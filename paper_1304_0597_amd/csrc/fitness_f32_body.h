@@ -44,7 +44,12 @@ __device__ __forceinline__ gptr_f32 global_f32(const float* p) { return (gptr_f3
 
 // Tile range [split's tiles] x chromosome tile ctile of the launch described
 // by a_in; writes a.partial[split * ld_partial + chromosome].  genes: the
-// chromosomes being scored; lds: the workgroup's dynamic LDS.
+// chromosomes being scored; lds: the workgroup's dynamic LDS.  D is the
+// degree, or 0 for the degree a_in.degree read at run time: the same
+// K-steps in the same order with the same recurrence arithmetic, so both
+// forms give the same bits (the batched kernel runs every run's degree
+// through one body this way).  BASIS is the expansion family, or -1 for the
+// family a_in.basis read at run time, likewise.
 template <int BASIS, int D>
 __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const float* __restrict__ genes,
                                                   int split, int ctile, float* lds) {
@@ -68,6 +73,9 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   a.n_tiles = uniform(a_in.n_tiles);
   a.error_fn = uniform(a_in.error_fn);
   a.R = uniform(a_in.R);
+  const int Dv = D > 0 ? D : uniform(a_in.degree);
+  const int fam = BASIS >= 0 ? BASIS : uniform(a_in.basis);
+  const bool trig = fam == 3;
   genes = uniform(genes);
   split = uniform(split);
   ctile = uniform(ctile);
@@ -79,7 +87,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   const int c0 = ctile * kTileCols;
 
   const int ppc = a.pairs_per_chunk;
-  const int SC = ppc * D;          // K-steps per chunk
+  const int SC = ppc * Dv;         // K-steps per chunk
   const int WS = 2 * SC + 1;       // LDS row stride in floats (odd)
   const int BUF = kTileCols * WS;  // floats per gene buffer
   const int nk = (2 * SC + 63) >> 6;  // 64-gene pieces of a row
@@ -102,9 +110,9 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   auto stage_issue = [&](int chunk, int buf) {
     const int u0 = chunk * ppc * 2;
     const int rem = a.U - u0;
-    const int valid = min(2 * SC, rem * D);
+    const int valid = min(2 * SC, rem * Dv);
     float* dst0 = lds + buf * BUF;
-    const float* src0 = genes + 1 + u0 * D + lane;
+    const float* src0 = genes + 1 + u0 * Dv + lane;
     for (int i = wave_u; i < kTileCols * nk; i += kFitThreads / 64) {
       const int c = i / nk;
       const int k = i - c * nk;
@@ -115,9 +123,9 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
             (__attribute__((address_space(3))) void*)(dst0 + c * WS + k * 64), 4, 0, 0);
     }
     if ((rem & 1) && rem < 2 * ppc) {
-      for (int idx = threadIdx.x; idx < kTileCols * D; idx += kFitThreads) {
-        const int c = idx / D;
-        dst0[c * WS + rem * D + (idx - c * D)] = 0.f;
+      for (int idx = threadIdx.x; idx < kTileCols * Dv; idx += kFitThreads) {
+        const int c = idx / Dv;
+        dst0[c * WS + rem * Dv + (idx - c * Dv)] = 0.f;
       }
     }
   };
@@ -137,8 +145,8 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   // x of sub-feature pair q for this lane's two rows (0 outside the data).
   auto load_x = [&](int64_t row0, int q, float (&xo)[2]) {
     const int u = 2 * q + h;
-    const int f = BASIS == 3 ? q : u;
-    const bool fvalid = BASIS == 3 ? true : (u < a.U);
+    const int f = trig ? q : u;
+    const bool fvalid = trig ? true : (u < a.U);
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
       const int64_t r = row0 + rb * 32 + m;
@@ -192,28 +200,43 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
         if (q + 1 < a.Q) load_x(row0, q + 1, xn);
         else if (tile + 1 < tile_end) load_x(row0 + kTileRows, 0, xn);
         Recur<BASIS> rc[2];
+        if constexpr (BASIS < 0) rc[0].fam = rc[1].fam = fam;
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) rc[rb].seed(x[rb], h);
-        const float* wl = wbuf + m * WS + (2 * (q - q_begin) + h) * D;
+        const float* wl = wbuf + m * WS + (2 * (q - q_begin) + h) * Dv;
         // One K-step per degree: two MFMA columns x two row blocks, then the
         // recurrence moves every lane's A value to the next degree.
-        auto kstep = [&](auto jc) {
-          constexpr int j = decltype(jc)::value;
-          const float b0 = wl[j];
-          const float b1 = wl[32 * WS + j];
+        auto mfma4 = [&](float b0, float b1) {
 #pragma unroll
           for (int rb = 0; rb < 2; ++rb) {
             acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(rc[rb].cur, b0, acc[rb][0], 0, 0, 0);
             acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(rc[rb].cur, b1, acc[rb][1], 0, 0, 0);
           }
-          if constexpr (j + 1 < D) {
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb) rc[rb].template advance<j + 1>(x[rb]);
-          }
         };
-        [&]<int... J>(std::integer_sequence<int, J...>) {
-          (kstep(std::integral_constant<int, J>{}), ...);
-        }(std::make_integer_sequence<int, D>{});
+        if constexpr (D > 0) {
+          auto kstep = [&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            mfma4(wl[j], wl[32 * WS + j]);
+            if constexpr (j + 1 < D) {
+#pragma unroll
+              for (int rb = 0; rb < 2; ++rb) rc[rb].template advance<j + 1>(x[rb]);
+            }
+          };
+          [&]<int... J>(std::integer_sequence<int, J...>) {
+            (kstep(std::integral_constant<int, J>{}), ...);
+          }(std::make_integer_sequence<int, D>{});
+        } else {
+          float b0 = wl[0], b1 = wl[32 * WS];
+          for (int j = 0; j + 1 < Dv; ++j) {
+            const float n0 = wl[j + 1], n1 = wl[32 * WS + j + 1];
+            mfma4(b0, b1);
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) rc[rb].advance_rt(j + 1, x[rb]);
+            b0 = n0;
+            b1 = n1;
+          }
+          mfma4(b0, b1);
+        }
       }
     }
 
