@@ -201,23 +201,36 @@ int game_init_population(game_t h);
  * build the next generation.  Once stopped, further steps do nothing. */
 int game_step(game_t h);
 
-/* Runs steps until a stop criterion holds, with the loop captured in a HIP
- * graph (no host round trip per generation); with a surrogate attached the
- * generations are queued on the stream in batches of 8 with a look at the
- * stop flag between batches instead (its few hundred short launches per
- * generation run faster that way).  Synchronises the stream.
- * max_generations < 0 and target < 0 keep the configured values.  Outputs
- * (each may be NULL): the number of evolution steps applied since the
- * last init/set, the best chromosome [K] and its float64 error. */
+/* The training loop of Sec. 4.1 (evaluate and sort, test the stop
+ * criteria, evolve) run to its stop criteria, the error threshold or the
+ * maximum number of iterations of Sec. 5.  The loop is captured in a HIP
+ * graph of 8 generations (no host round trip per generation); replays are
+ * queued two at a time with two such chunks in flight, and queuing ends once
+ * the device stop flag, copied back after each chunk, shows the run stopped
+ * (chunks queued meanwhile do nothing).  With a surrogate attached the
+ * generations are queued on the stream directly, 8 per chunk, with the same
+ * stop checks (its few hundred short launches per generation run faster
+ * that way).  Synchronises the stream.  max_generations < 0 and target < 0
+ * keep the configured values; a run that stopped on earlier limits resumes
+ * when its last evaluation no longer meets the new ones, and continues from
+ * that evaluation exactly as one uninterrupted run would have; otherwise
+ * nothing runs and the current results are reported.  Outputs (each may be NULL): the number of
+ * evolution steps applied since the last init/set, the best chromosome [K]
+ * and its float64 error. */
 int game_run(game_t h, int32_t max_generations, double target, int32_t* generations_done,
              float* best_genes_host, double* best_error_host);
 
-/* Current population [P x K] and, if fitness_dev is not NULL, its fitness
- * [P] as last evaluated (copies on the stream). */
+/* The "train" use case of Sec. 2 ends with the trained population stored:
+ * copies of the current population [P x K] and, if fitness_dev is not NULL,
+ * its fitness [P] as last evaluated (on the stream). */
 int game_get_population(game_t h, float* genes_dev, float* fitness_dev);
 
-/* Replaces the current population (resume from a stored population, the
- * "train" use case's output) and sets the generation counter. */
+/* Restores a stored population (the "train" use case's output, Sec. 2) to
+ * resume training from it: genes_dev [P x K] becomes the current population
+ * and the generation counter is set to `generation` (>= 0); the stop flag
+ * clears.  The next generation's draws are those of generation + 1, so a
+ * run resumed from the population and counter of step g continues exactly
+ * as the uninterrupted run. */
 int game_set_population(game_t h, const float* genes_dev, int32_t generation);
 
 /* Synchronises the stream and reports the generation counter, the stop
@@ -375,10 +388,20 @@ int game_batch_init(game_batch_t b);
 /* One generation of every run that has not stopped (three launches). */
 int game_batch_step(game_batch_t b);
 
+/* The evaluation half of a generation (Sec. 4.1, evaluate): the fitness of
+ * every running run's current population in one persistent launch, then
+ * the per-run fixed-order sums into each run's fitness [P] (as
+ * game_batch_get_population returns it); no ranking, stop test or genetic
+ * step.  The same work list and results as the evaluation inside
+ * game_batch_step. */
+int game_batch_evaluate(game_batch_t b);
+
 /* Runs every run until its stop criterion holds (its own max_generations
- * and target), by graph replay; synchronises.  Outputs per run (may be
- * NULL): evolution steps applied, best float64 error of the last
- * evaluation. */
+ * and target, Sec. 5), by replays of a captured graph of 4 generations,
+ * queued two at a time with two such chunks in flight until the run states
+ * copied back after a chunk show every run stopped; synchronises.  Outputs
+ * per run (may be NULL): evolution steps applied, best float64 error of the
+ * last evaluation. */
 int game_batch_run(game_batch_t b, int32_t* generations_done_host, double* best_error_host);
 
 /* Current population [P x K] of one run and its last fitness [P]. */

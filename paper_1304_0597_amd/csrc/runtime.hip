@@ -57,8 +57,9 @@ int check_config(const game_config* c, int32_t n_features) {
     return fail(GAME_EINVAL, "degree %d not in 1..%d", c->degree, kMaxDegree);
   if (c->population < 2 || c->population > kMaxPopulation)
     return fail(GAME_EINVAL, "population %d not in 2..%d", c->population, kMaxPopulation);
-  if (c->tournament_k < 1 || c->tournament_k > c->population || c->tournament_k > 64)
-    return fail(GAME_EINVAL, "tournament_k %d not in 1..min(population, 64)", c->tournament_k);
+  if (c->tournament_k < 1 || c->tournament_k > c->population)
+    return fail(GAME_EINVAL, "tournament_k %d not in 1..population (%d)", c->tournament_k,
+                c->population);
   if (c->elitism < 0 || c->elitism >= c->population)
     return fail(GAME_EINVAL, "elitism %d not in 0..population-1", c->elitism);
   if (c->elite_mode != 0 && c->elite_mode != 1)
@@ -137,6 +138,8 @@ struct game_ctx {
   hipGraphExec_t graph;
   int graph_steps;
   game_surrogate_ctx* sur;  // attached fitness surrogate (screening), or null
+  RunState* host_state;     // two pinned host slots for the stop checks of game_run
+  hipEvent_t chunk_done[2];
 };
 
 struct game_surrogate_ctx {
@@ -454,6 +457,28 @@ int enqueue_screening(game_ctx* h, hipStream_t s) {
   return GAME_OK;
 }
 
+// The rest of a generation after its stop test: the roulette wheel when
+// selecting by roulette, then the genetic step (or, with a surrogate, the
+// screened generation tail) building pop[gen & 1] for the advanced counter.
+// Every kernel does nothing once the run has stopped.
+int enqueue_tail(game_ctx* h, hipStream_t s) {
+  if (h->cfg.selection == GAME_ROULETTE)
+    GAME_HIP(launch_roulette_cum(h->fit32, h->cfg.population, h->cum, &h->state->stop, s));
+  if (h->sur) return enqueue_screening(h, s);
+  GAArgs ga = ga_args(&h->cfg, h->K);
+  ga.cum = h->cum;
+  ga.pop_a = h->pop[0];
+  ga.pop_b = h->pop[1];
+  ga.out_a = h->pop[0];
+  ga.out_b = h->pop[1];
+  ga.fitness = h->fit32;
+  ga.order = h->order;
+  ga.gen_ptr = &h->state->gen;
+  ga.stop = &h->state->stop;
+  GAME_HIP(launch_ga_next(ga, s));
+  return GAME_OK;
+}
+
 // One generation of the loop on stream s: evaluate pop[gen & 1], finish and
 // rank, stop test, then build pop[(gen + 1) & 1].
 int enqueue_step(game_ctx* h, hipStream_t s) {
@@ -476,21 +501,7 @@ int enqueue_step(game_ctx* h, hipStream_t s) {
   ra.state = h->state;
   GAME_HIP(launch_reduce_fitness(ra, s));
   GAME_HIP(launch_finish_rank(ra, s));
-  if (h->cfg.selection == GAME_ROULETTE)
-    GAME_HIP(launch_roulette_cum(h->fit32, h->cfg.population, h->cum, &h->state->stop, s));
-  if (h->sur) return enqueue_screening(h, s);
-  GAArgs ga = ga_args(&h->cfg, h->K);
-  ga.cum = h->cum;
-  ga.pop_a = h->pop[0];
-  ga.pop_b = h->pop[1];
-  ga.out_a = h->pop[0];
-  ga.out_b = h->pop[1];
-  ga.fitness = h->fit32;
-  ga.order = h->order;
-  ga.gen_ptr = &h->state->gen;
-  ga.stop = &h->state->stop;
-  GAME_HIP(launch_ga_next(ga, s));
-  return GAME_OK;
+  return enqueue_tail(h, s);
 }
 
 __global__ void copy_current_kernel(const RunState* st, const float* pop0, const float* pop1,
@@ -499,6 +510,47 @@ __global__ void copy_current_kernel(const RunState* st, const float* pop0, const
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     out[i] = src[i];
+}
+
+// Queues up to n_chunks chunks of generations (enqueue() queues one) with
+// two chunks in flight: after each chunk the n run states are copied to one
+// of two pinned host slots and an event is recorded; before queuing chunk i
+// the host waits for chunk i - 2's copy and stops queuing once every run had
+// stopped by then.  Chunks queued after a stop do nothing (every kernel reads
+// the device stop flag), so at most two chunks run idle.
+template <class F>
+int queue_chunks(hipStream_t s, int64_t n_chunks, const RunState* dev, int n, RunState* slots,
+                 hipEvent_t* done, F&& enqueue) {
+  for (int64_t i = 0; i < n_chunks; ++i) {
+    RunState* slot = slots + (i & 1) * n;
+    if (i >= 2) {
+      GAME_HIP(hipEventSynchronize(done[i & 1]));
+      bool all = true;
+      for (int r = 0; r < n && all; ++r) all = slot[r].stop != 0;
+      if (all) break;
+    }
+    const int rc = enqueue();
+    if (rc) return rc;
+    GAME_HIP(hipMemcpyAsync(slot, dev, sizeof(RunState) * n, hipMemcpyDeviceToHost, s));
+    GAME_HIP(hipEventRecord(done[i & 1], s));
+  }
+  return GAME_OK;
+}
+
+// Pinned host slots and events for queue_chunks over n run states.
+int create_chunk_sync(int n, RunState** slots, hipEvent_t* done) {
+  *slots = nullptr;
+  done[0] = done[1] = nullptr;
+  GAME_HIP(hipHostMalloc((void**)slots, 2 * sizeof(RunState) * n, hipHostMallocDefault));
+  for (int i = 0; i < 2; ++i)
+    GAME_HIP(hipEventCreateWithFlags(&done[i], hipEventDisableTiming));
+  return GAME_OK;
+}
+
+void destroy_chunk_sync(RunState* slots, hipEvent_t* done) {
+  for (int i = 0; i < 2; ++i)
+    if (done[i]) (void)hipEventDestroy(done[i]);
+  if (slots) (void)hipHostFree(slots);
 }
 
 }  // namespace
@@ -580,11 +632,16 @@ int game_create(const game_config* c, const float* X, const float* t, int64_t NP
     delete h;
     return hip_fail(e, "hipStreamCreateWithFlags");
   }
-  e = launch_set_state(h->state, 0, c->max_generations, c->target, 1, h->stream);
-  if (e != hipSuccess) {
-    hipStreamDestroy(h->capture_stream);
+  rc = create_chunk_sync(1, &h->host_state, h->chunk_done);
+  if (rc == GAME_OK) {
+    e = launch_set_state(h->state, 0, c->max_generations, c->target, 1, h->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "launch_set_state");
+  }
+  if (rc) {
+    destroy_chunk_sync(h->host_state, h->chunk_done);
+    (void)hipStreamDestroy(h->capture_stream);
     delete h;
-    return hip_fail(e, "launch_set_state");
+    return rc;
   }
   *out = h;
   return GAME_OK;
@@ -592,8 +649,9 @@ int game_create(const game_config* c, const float* X, const float* t, int64_t NP
 
 int game_destroy(game_t h) {
   if (!h) return fail(GAME_EINVAL, "handle is NULL");
-  if (h->graph) hipGraphExecDestroy(h->graph);
-  if (h->capture_stream) hipStreamDestroy(h->capture_stream);
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+  destroy_chunk_sync(h->host_state, h->chunk_done);
   delete h;
   return GAME_OK;
 }
@@ -733,50 +791,75 @@ int game_run(game_t h, int32_t max_gen, double target, int32_t* gens_done, float
   if (!h->initialized) return fail(GAME_ESTATE, "population not initialised");
   if (max_gen >= 0) h->cfg.max_generations = max_gen;
   if (target >= 0) h->cfg.target = target;
-  GAME_HIP(launch_set_state(h->state, 0, h->cfg.max_generations, h->cfg.target, 0, h->stream));
   RunState st{};
   GAME_HIP(hipMemcpyAsync(&st, h->state, sizeof st, hipMemcpyDeviceToHost, h->stream));
   GAME_HIP(hipStreamSynchronize(h->stream));
-  if (h->sur) {
+  // A run stopped on its last evaluation continues from it when that
+  // evaluation meets neither new criterion: the stop test's other branch
+  // (the counter advances), then the rest of that generation, exactly as
+  // one uninterrupted run would have gone on.
+  const bool resume = st.stop && st.evaluated == st.gen &&
+                      !(st.best_err <= h->cfg.target || st.gen >= h->cfg.max_generations);
+  GAME_HIP(launch_set_state(h->state, 0, h->cfg.max_generations, h->cfg.target, resume ? 2 : 0,
+                            h->stream));
+  if (resume) {
+    const int rc = enqueue_tail(h, h->stream);
+    if (rc) return rc;
+    st.stop = 0;
+    st.gen += 1;
+  }
+  // Evaluations left (at least one: a run past its limit evaluates once and
+  // stops).
+  const int64_t evals = std::max<int64_t>(1, (int64_t)h->cfg.max_generations - st.gen + 1);
+  if (h->sur && !st.stop) {
     // A screened generation is a few hundred short launches; the stream runs
     // them back to back faster than a graph replays them, so generations
-    // are queued directly, 8 at a time, with a look at the stop flag between
-    // batches (steps queued after the stop do nothing).
-    while (!st.stop) {
-      for (int i = 0; i < 8; ++i) {
-        const int rc = enqueue_step(h, h->stream);
-        if (rc) return rc;
+    // are queued directly, 8 per chunk.
+    int64_t left = evals;
+    const int rc = queue_chunks(h->stream, (evals + 7) / 8, h->state, 1, h->host_state,
+                                h->chunk_done, [&]() {
+                                  for (int i = 0; i < 8 && left > 0; ++i, --left) {
+                                    const int r = enqueue_step(h, h->stream);
+                                    if (r) return r;
+                                  }
+                                  return (int)GAME_OK;
+                                });
+    if (rc) return rc;
+  } else if (!st.stop) {
+    if (!h->graph) {
+      // Capture a fixed number of generations once; every kernel reads the
+      // generation counter and the stop flag from device memory, so the
+      // same graph serves every replay and does nothing once stopped.
+      const int steps = 8;
+      GAME_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
+      int rc = GAME_OK;
+      for (int i = 0; i < steps && rc == GAME_OK; ++i) rc = enqueue_step(h, h->capture_stream);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(h->capture_stream, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
       }
-      GAME_HIP(hipMemcpyAsync(&st, h->state, sizeof st, hipMemcpyDeviceToHost, h->stream));
-      GAME_HIP(hipStreamSynchronize(h->stream));
+      if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+      const hipError_t ei = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        h->graph = nullptr;
+        return hip_fail(ei, "hipGraphInstantiate");
+      }
+      h->graph_steps = steps;
     }
-  } else if (!h->graph) {
-    // Capture a fixed number of generations once; every kernel reads the
-    // generation counter and the stop flag from device memory, so the same
-    // graph serves every replay and does nothing once stopped.
-    const int steps = 8;
-    GAME_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
-    int rc = GAME_OK;
-    for (int i = 0; i < steps && rc == GAME_OK; ++i) rc = enqueue_step(h, h->capture_stream);
-    hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(h->capture_stream, &g);
-    if (rc) {
-      if (g) hipGraphDestroy(g);
-      return rc;
-    }
-    if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
-    const hipError_t ei = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    if (ei != hipSuccess) {
-      h->graph = nullptr;
-      return hip_fail(ei, "hipGraphInstantiate");
-    }
-    h->graph_steps = steps;
-  }
-  if (!st.stop && !h->sur) {
-    const int64_t evals = (int64_t)h->cfg.max_generations - st.gen + 1;
-    const int64_t launches = evals <= 0 ? 1 : (evals + h->graph_steps - 1) / h->graph_steps;
-    for (int64_t i = 0; i < launches; ++i) GAME_HIP(hipGraphLaunch(h->graph, h->stream));
+    // Two replays (16 generations) per chunk.
+    const int64_t launches = (evals + h->graph_steps - 1) / h->graph_steps;
+    const int rc = queue_chunks(h->stream, (launches + 1) / 2, h->state, 1, h->host_state,
+                                h->chunk_done, [&]() {
+                                  for (int i = 0; i < 2; ++i) {
+                                    const hipError_t e = hipGraphLaunch(h->graph, h->stream);
+                                    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+                                  }
+                                  return (int)GAME_OK;
+                                });
+    if (rc) return rc;
   }
   GAME_HIP(hipMemcpyAsync(&st, h->state, sizeof st, hipMemcpyDeviceToHost, h->stream));
   GAME_HIP(hipStreamSynchronize(h->stream));
@@ -1067,7 +1150,7 @@ int game_attach_surrogate(game_t h, game_surrogate_t s) {
   }
   h->sur = s;
   if (h->graph) {
-    hipGraphExecDestroy(h->graph);
+    (void)hipGraphExecDestroy(h->graph);
     h->graph = nullptr;
   }
   return GAME_OK;
@@ -1116,6 +1199,8 @@ struct game_batch_ctx {
   int graph_steps;
   bool initialized;
   bool any_roulette;
+  RunState* host_states;    // two pinned host slots of n_runs states (game_batch_run)
+  hipEvent_t chunk_done[2];
 };
 
 namespace {
@@ -1229,7 +1314,7 @@ int build_items(game_batch_ctx* b, int32_t tiles) {
   b->n_items = (int32_t)items.size();
   b->tiles_per_item = tiles;
   if (b->graph) {
-    hipGraphExecDestroy(b->graph);
+    (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
   }
   return GAME_OK;
@@ -1371,9 +1456,11 @@ int game_batch_create(const game_run_desc* runs, int32_t n_runs, void* ws, size_
                          hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) rc = hip_fail(e, "hipMemcpyAsync");
   }
+  if (!rc) rc = create_chunk_sync(n_runs, &b->host_states, b->chunk_done);
   if (!rc) rc = build_items(b, 8);
   if (rc) {
-    if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+    destroy_chunk_sync(b->host_states, b->chunk_done);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     delete b;
     return rc;
   }
@@ -1383,8 +1470,9 @@ int game_batch_create(const game_run_desc* runs, int32_t n_runs, void* ws, size_
 
 int game_batch_destroy(game_batch_t b) {
   if (!b) return fail(GAME_EINVAL, "batch is NULL");
-  if (b->graph) hipGraphExecDestroy(b->graph);
-  if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  destroy_chunk_sync(b->host_states, b->chunk_done);
   delete b;
   return GAME_OK;
 }
@@ -1441,8 +1529,8 @@ int game_batch_autotune(game_batch_t b, int32_t reps, int32_t* best_tiles, int32
     }
     if (rc) break;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc) return rc;
   b->grid = bg;
   rc = build_items(b, bt);
@@ -1473,6 +1561,18 @@ int game_batch_step(game_batch_t b) {
   return enqueue_batch_step(b, b->stream);
 }
 
+int game_batch_evaluate(game_batch_t b) {
+  if (!b) return fail(GAME_EINVAL, "batch is NULL");
+  if (!b->initialized) return fail(GAME_ESTATE, "batch not initialised");
+  const BatchArgs a = batch_args(b);
+  GAME_HIP(launch_batch_reset(a, b->stream));
+  GAME_HIP(launch_fitness_batch(a, b->lds, b->stream));
+  GAME_HIP(launch_reduce_fitness_batch(a, b->stream));
+  // the queues are re-armed for the next generation's launch
+  GAME_HIP(launch_batch_reset(a, b->stream));
+  return GAME_OK;
+}
+
 int game_batch_run(game_batch_t b, int32_t* gens_done, double* best_err) {
   if (!b) return fail(GAME_EINVAL, "batch is NULL");
   if (!b->initialized) return fail(GAME_ESTATE, "batch not initialised");
@@ -1492,21 +1592,30 @@ int game_batch_run(game_batch_t b, int32_t* gens_done, double* best_err) {
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(b->capture_stream, &g);
       if (rc) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc;
       }
       if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
       const hipError_t ei = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       if (ei != hipSuccess) {
         b->graph = nullptr;
         return hip_fail(ei, "hipGraphInstantiate");
       }
       b->graph_steps = steps;
     }
-    const int64_t evals = (int64_t)b->max_gen - min_gen + 1;
-    const int64_t launches = evals <= 0 ? 1 : (evals + b->graph_steps - 1) / b->graph_steps;
-    for (int64_t i = 0; i < launches; ++i) GAME_HIP(hipGraphLaunch(b->graph, b->stream));
+    // Two replays (8 generations) per chunk, until every run has stopped.
+    const int64_t evals = std::max<int64_t>(1, (int64_t)b->max_gen - min_gen + 1);
+    const int64_t launches = (evals + b->graph_steps - 1) / b->graph_steps;
+    const int rc = queue_chunks(b->stream, (launches + 1) / 2, b->states, b->n_runs,
+                                b->host_states, b->chunk_done, [&]() {
+                                  for (int i = 0; i < 2; ++i) {
+                                    const hipError_t e = hipGraphLaunch(b->graph, b->stream);
+                                    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+                                  }
+                                  return (int)GAME_OK;
+                                });
+    if (rc) return rc;
   }
   GAME_HIP(hipMemcpyAsync(st.data(), b->states, sizeof(RunState) * b->n_runs,
                           hipMemcpyDeviceToHost, b->stream));

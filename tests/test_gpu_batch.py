@@ -194,3 +194,24 @@ def test_batch_error_functions_follow_single_runs(gg):
         assert abs(best[r] - err) <= 1e-12 * max(err, 1e-30), r
         g.close()
     b.close()
+
+
+def test_batch_evaluate_is_the_steps_evaluation(gg):
+    """game_batch_evaluate gives each run exactly the fitness the next
+    generation's evaluation gives (same work list, same sums), and leaves
+    the queues ready for that generation."""
+    problems, cfgs, host = make_runs(gg)
+    b = gg.Batch(problems, cfgs)
+    b.init()
+    b.step()
+    b.evaluate()
+    ev = [b.population(r)[1].cpu().numpy().copy() for r in range(b.n_runs)]
+    pops = [b.population(r)[0].cpu().numpy().copy() for r in range(b.n_runs)]
+    b.step()
+    for r, c in enumerate(cfgs):
+        fit = b.population(r)[1].cpu().numpy()
+        assert np.array_equal(ev[r].view(np.uint32), fit.view(np.uint32)), r
+        X, t = host[r]
+        ref = og.fitness(X, t, pops[r], c.basis, c.degree)
+        assert np.all(np.abs(ev[r] - ref) <= 1e-5 * ref + 1e-7 * np.mean(t.astype(np.float64) ** 2))
+    b.close()
