@@ -109,6 +109,7 @@ _SIGS = {
                                       POINTER(c_float), c_void_p]),
     "game_batch_init": (c_int32, [c_void_p]),
     "game_batch_step": (c_int32, [c_void_p]),
+    "game_batch_evaluate": (c_int32, [c_void_p]),
     "game_batch_run": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "game_batch_get_population": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "game_batch_num_items": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32),
@@ -158,6 +159,50 @@ def _ptr(t, dtype=None) -> int:
     return t.data_ptr()
 
 
+# Sizes of every live handle, recorded by the create calls: the shape checks
+# below compare each tensor with them before anything reaches the library,
+# so a mismatched tensor raises ValueError instead of a kernel reading or
+# writing past an allocation.
+_handles: dict = {}
+
+
+def _dims(h) -> dict:
+    try:
+        return _handles[h]
+    except KeyError:
+        raise ValueError("unknown handle (not created here, or already destroyed)") from None
+
+
+def _shape(t, shape, name) -> None:
+    """t (if not None) has exactly `shape`; None entries match any size."""
+    if t is None:
+        return
+    got = tuple(t.shape)
+    if len(got) != len(shape) or any(e is not None and g != e for g, e in zip(got, shape)):
+        want = "x".join("*" if e is None else str(e) for e in shape)
+        raise ValueError(f"{name}: expected shape [{want}], got {list(got)}")
+
+
+def _rows(t, n, cols, name) -> None:
+    """t is [rows x cols] with at least n rows (n chromosomes read or written)."""
+    _shape(t, (None, cols), name)
+    if t.shape[0] < n:
+        raise ValueError(f"{name}: {t.shape[0]} rows, the call uses {n}")
+
+
+def _numel(t, n, name) -> None:
+    """t (if not None) has at least n elements."""
+    if t is not None and t.numel() < n:
+        raise ValueError(f"{name}: {t.numel()} elements, the call uses {n}")
+
+
+def _data(X, t, n_features, name="X") -> None:
+    """A data set: X [NP x N] with the expected N, t [NP] (if given)."""
+    _shape(X, (None, n_features), name)
+    if t is not None:
+        _shape(t, (X.shape[0],), "t")
+
+
 def _stream(stream) -> int:
     import torch
     if stream is None:
@@ -193,26 +238,39 @@ def game_workspace_size(cfg: game_config, n_patterns: int, n_features: int) -> i
 
 def game_create(cfg, X, t, workspace, stream=None) -> int:
     import torch
+    _shape(X, (None, None), "X")
+    _shape(t, (X.shape[0],), "t")
+    K = game_num_genes(cfg, X.shape[1])
     h = c_void_p()
     _check(lib().game_create(ctypes.byref(cfg), _ptr(X, torch.float32), _ptr(t, torch.float32),
                              X.shape[0], X.shape[1], _ptr(workspace),
                              workspace.numel() * workspace.element_size(), _stream(stream),
                              ctypes.byref(h)))
+    _handles[h.value] = {"n_patterns": X.shape[0], "n_features": X.shape[1], "n_genes": K,
+                         "population": cfg.population}
     return h.value
 
 
 def game_destroy(h) -> None:
     _check(lib().game_destroy(h))
+    _handles.pop(h, None)
 
 
 def game_fitness(h, genes, n, fitness, fitness64=None) -> None:
     import torch
+    _rows(genes, n, _dims(h)["n_genes"], "genes")
+    _numel(fitness, n, "fitness")
+    _numel(fitness64, n, "fitness64")
     _check(lib().game_fitness(h, _ptr(genes, torch.float32), n, _ptr(fitness, torch.float32),
                               _ptr(fitness64, torch.float64)))
 
 
 def game_evaluate(h, X, t, genes, n, err64) -> None:
     import torch
+    d = _dims(h)
+    _data(X, t, d["n_features"])
+    _rows(genes, n, d["n_genes"], "genes")
+    _numel(err64, n, "err64")
     _check(lib().game_evaluate(h, _ptr(X, torch.float32), _ptr(t, torch.float32), X.shape[0],
                                _ptr(genes, torch.float32), n, _ptr(err64, torch.float64)))
 
@@ -220,6 +278,10 @@ def game_evaluate(h, X, t, genes, n, err64) -> None:
 def game_rescore64(h, X, t, genes, n, err64) -> None:
     """X, t None -> the handle's own data set."""
     import torch
+    d = _dims(h)
+    _data(X, t, d["n_features"])
+    _rows(genes, n, d["n_genes"], "genes")
+    _numel(err64, n, "err64")
     n_patterns = X.shape[0] if X is not None else 0
     _check(lib().game_rescore64(h, _ptr(X, torch.float32), _ptr(t, torch.float32), n_patterns,
                                 _ptr(genes, torch.float32), n, _ptr(err64, torch.float64)))
@@ -228,6 +290,11 @@ def game_rescore64(h, X, t, genes, n, err64) -> None:
 def game_predict(h, X, genes, n, out) -> None:
     """X None -> the handle's own data set."""
     import torch
+    d = _dims(h)
+    _data(X, None, d["n_features"])
+    n_patterns = X.shape[0] if X is not None else d["n_patterns"]
+    _rows(genes, n, d["n_genes"], "genes")
+    _rows(out, n, n_patterns, "out")
     n_patterns = X.shape[0] if X is not None else 0
     _check(lib().game_predict(h, _ptr(X, torch.float32), n_patterns, _ptr(genes, torch.float32),
                               n, _ptr(out, torch.float32)))
@@ -236,6 +303,10 @@ def game_predict(h, X, genes, n, out) -> None:
 def game_classify(h, X, t, genes, n, threshold, counts) -> None:
     """X, t None -> the handle's own data set."""
     import torch
+    d = _dims(h)
+    _data(X, t, d["n_features"])
+    _rows(genes, n, d["n_genes"], "genes")
+    _rows(counts, n, 4, "counts")
     n_patterns = X.shape[0] if X is not None else 0
     _check(lib().game_classify(h, _ptr(X, torch.float32), _ptr(t, torch.float32), n_patterns,
                                _ptr(genes, torch.float32), n, threshold,
@@ -245,8 +316,11 @@ def game_classify(h, X, t, genes, n, threshold, counts) -> None:
 def game_trig_sums(X, degree: int, Z=None, stream=None):
     """Per-pattern cos/sin sums of the shared-gene model: Z [NP x 2*degree]."""
     import torch
+    _shape(X, (None, None), "X")
     if Z is None:
         Z = torch.empty((X.shape[0], 2 * degree), dtype=torch.float32, device=X.device)
+    if 1 <= degree <= 16:      # other degrees are the library's to reject
+        _shape(Z, (X.shape[0], 2 * degree), "Z")
     _check(lib().game_trig_sums(_ptr(X, torch.float32), X.shape[0], X.shape[1], degree,
                                 _ptr(Z, torch.float32), _stream(stream)))
     return Z
@@ -271,6 +345,8 @@ def game_step(h) -> None:
 
 def game_run(h, n_genes: int, max_generations: int = -1, target: float = -1.0):
     """Returns (generations_done, best_genes [K] float32 numpy, best_error)."""
+    if n_genes != _dims(h)["n_genes"]:
+        raise ValueError(f"n_genes {n_genes}, the handle has {_dims(h)['n_genes']}")
     gens = c_int32()
     best = np.zeros(n_genes, dtype=np.float32)
     err = c_double()
@@ -281,11 +357,16 @@ def game_run(h, n_genes: int, max_generations: int = -1, target: float = -1.0):
 
 def game_get_population(h, genes, fitness=None) -> None:
     import torch
+    d = _dims(h)
+    _shape(genes, (d["population"], d["n_genes"]), "genes")
+    _shape(fitness, (d["population"],), "fitness")
     _check(lib().game_get_population(h, _ptr(genes, torch.float32), _ptr(fitness, torch.float32)))
 
 
 def game_set_population(h, genes, generation: int) -> None:
     import torch
+    d = _dims(h)
+    _shape(genes, (d["population"], d["n_genes"]), "genes")
     _check(lib().game_set_population(h, _ptr(genes, torch.float32), generation))
 
 
@@ -299,6 +380,8 @@ def game_get_state(h) -> dict:
 
 def game_rank(fitness, n, order, stream=None) -> None:
     import torch
+    _numel(fitness, n, "fitness")
+    _numel(order, n, "order")
     _check(lib().game_rank(_ptr(fitness, torch.float32), n, _ptr(order, torch.int32),
                            _stream(stream)))
 
@@ -312,6 +395,9 @@ def game_ga_workspace_size(cfg) -> int:
 
 def game_ga_next(cfg, n_genes, pop, fitness, generation, out, workspace, stream=None) -> None:
     import torch
+    _shape(pop, (cfg.population, n_genes), "pop")
+    _shape(fitness, (cfg.population,), "fitness")
+    _shape(out, (cfg.population, n_genes), "out")
     _check(lib().game_ga_next(ctypes.byref(cfg), n_genes, _ptr(pop, torch.float32),
                               _ptr(fitness, torch.float32), generation, _ptr(out, torch.float32),
                               _ptr(workspace), workspace.numel() * workspace.element_size(),
@@ -320,6 +406,7 @@ def game_ga_next(cfg, n_genes, pop, fitness, generation, out, workspace, stream=
 
 def game_init_genes(cfg, n_genes, out, stream=None) -> None:
     import torch
+    _shape(out, (cfg.population, n_genes), "out")
     _check(lib().game_init_genes(ctypes.byref(cfg), n_genes, _ptr(out, torch.float32),
                                  _stream(stream)))
 
@@ -415,6 +502,7 @@ def _descs(problems, cfgs):
     import torch
     arr = (game_run_desc * len(problems))()
     for i, ((X, t), c) in enumerate(zip(problems, cfgs)):
+        _data(X, t, None, f"run {i}: X")
         arr[i].X_dev = _ptr(X, torch.float32)
         arr[i].t_dev = _ptr(t, torch.float32)
         arr[i].n_patterns = X.shape[0]
@@ -432,15 +520,21 @@ def game_batch_workspace_size(descs, n_runs) -> int:
 
 
 def game_batch_create(descs, n_runs, workspace, stream=None) -> int:
+    if n_runs > len(descs):
+        raise ValueError(f"{len(descs)} run descriptors, the call uses {n_runs}")
+    runs = [{"population": descs[i].cfg.population,
+             "n_genes": game_num_genes(descs[i].cfg, descs[i].n_features)} for i in range(n_runs)]
     h = c_void_p()
     _check(lib().game_batch_create(descs, n_runs, _ptr(workspace),
                                    workspace.numel() * workspace.element_size(), _stream(stream),
                                    ctypes.byref(h)))
+    _handles[h.value] = {"runs": runs}
     return h.value
 
 
 def game_batch_destroy(b) -> None:
     _check(lib().game_batch_destroy(b))
+    _handles.pop(b, None)
 
 
 def game_batch_tune(b, tiles_per_item, grid) -> None:
@@ -465,7 +559,13 @@ def game_batch_step(b) -> None:
     _check(lib().game_batch_step(b))
 
 
+def game_batch_evaluate(b) -> None:
+    _check(lib().game_batch_evaluate(b))
+
+
 def game_batch_run(b, n_runs):
+    if n_runs != len(_dims(b)["runs"]):
+        raise ValueError(f"n_runs {n_runs}, the batch has {len(_dims(b)['runs'])}")
     gens = np.zeros(n_runs, dtype=np.int32)
     best = np.zeros(n_runs, dtype=np.float64)
     _check(lib().game_batch_run(b, gens.ctypes.data_as(c_void_p), best.ctypes.data_as(c_void_p)))
@@ -474,6 +574,11 @@ def game_batch_run(b, n_runs):
 
 def game_batch_get_population(b, run, genes, fitness=None) -> None:
     import torch
+    runs = _dims(b)["runs"]
+    if not 0 <= run < len(runs):
+        raise ValueError(f"run {run} not in 0..{len(runs) - 1}")
+    _shape(genes, (runs[run]["population"], runs[run]["n_genes"]), "genes")
+    _shape(fitness, (runs[run]["population"],), "fitness")
     _check(lib().game_batch_get_population(b, run, _ptr(genes, torch.float32),
                                            _ptr(fitness, torch.float32)))
 
@@ -522,6 +627,9 @@ class Batch:
     def step(self):
         game_batch_step(self.h)
 
+    def evaluate(self):
+        game_batch_evaluate(self.h)
+
     def run(self):
         return game_batch_run(self.h, self.n_runs)
 
@@ -565,11 +673,15 @@ def game_surrogate_create(cfg, n_genes, max_batch, workspace, stream=None) -> in
     _check(lib().game_surrogate_create(ctypes.byref(cfg), n_genes, max_batch, _ptr(workspace),
                                        workspace.numel() * workspace.element_size(),
                                        _stream(stream), ctypes.byref(h)))
+    _handles[h.value] = {"n_genes": n_genes, "max_batch": max_batch,
+                         "minibatch": cfg.minibatch,
+                         "n_params": lib().game_surrogate_num_params(h.value)}
     return h.value
 
 
 def game_surrogate_destroy(s) -> None:
     _check(lib().game_surrogate_destroy(s))
+    _handles.pop(s, None)
 
 
 def game_surrogate_num_params(s) -> int:
@@ -578,21 +690,30 @@ def game_surrogate_num_params(s) -> int:
 
 def game_surrogate_get_params(s, params) -> None:
     import torch
+    _numel(params, _dims(s)["n_params"], "params")
     _check(lib().game_surrogate_get_params(s, _ptr(params, torch.float32)))
 
 
 def game_surrogate_set_params(s, params) -> None:
     import torch
+    _numel(params, _dims(s)["n_params"], "params")
     _check(lib().game_surrogate_set_params(s, _ptr(params, torch.float32)))
 
 
 def game_surrogate_predict(s, genes, n, y) -> None:
     import torch
+    _rows(genes, n, _dims(s)["n_genes"], "genes")
+    _numel(y, n, "y")
     _check(lib().game_surrogate_predict(s, _ptr(genes, torch.float32), n, _ptr(y, torch.float32)))
 
 
 def game_surrogate_gradients(s, genes, target, n, grads, y=None) -> None:
     import torch
+    d = _dims(s)
+    _rows(genes, n, d["n_genes"], "genes")
+    _numel(target, n, "target")
+    _numel(grads, d["n_params"], "grads")
+    _numel(y, n, "y")
     _check(lib().game_surrogate_gradients(s, _ptr(genes, torch.float32),
                                           _ptr(target, torch.float32), n,
                                           _ptr(grads, torch.float32), _ptr(y, torch.float32)))
@@ -600,6 +721,8 @@ def game_surrogate_gradients(s, genes, target, n, grads, y=None) -> None:
 
 def game_surrogate_train_step(s, genes, target, n) -> None:
     import torch
+    _rows(genes, n, _dims(s)["n_genes"], "genes")
+    _numel(target, n, "target")
     _check(lib().game_surrogate_train_step(s, _ptr(genes, torch.float32),
                                            _ptr(target, torch.float32), n))
 

@@ -63,7 +63,7 @@ def test_defaults_and_gene_counts():
 
 @pytest.mark.parametrize("field,value", [
     ("basis", 4), ("degree", 0), ("degree", 17), ("population", 1), ("population", 8193),
-    ("tournament_k", 0), ("tournament_k", 65), ("elitism", 50), ("elite_mode", 2),
+    ("tournament_k", 0), ("tournament_k", 51), ("elitism", 50), ("elite_mode", 2),
     ("init_mode", 3), ("error_fn", 4), ("p_crossover", 1.5), ("p_mutation", -0.1),
     ("sigma_mutation", -1.0), ("max_generations", -1), ("selection", 3), ("selection", -1),
 ])
@@ -75,6 +75,35 @@ def test_invalid_configs_are_rejected(field, value):
     assert ei.value.code == game.GAME_EINVAL
     assert game.game_last_error()
     assert game.lib().game_workspace_size(ctypes.byref(c), 100, 7) == 0
+
+
+def _documented_range(field):
+    """The 'lo..hi' range the header's comment gives for a game_config field."""
+    src = open(HEADER).read()
+    m = re.search(r"int32_t\s+" + field + r";\s*/\*\s*(\S+)\.\.(\S+)", src)
+    assert m, field
+    return m.group(1), m.group(2)
+
+
+def test_documented_ranges_are_the_enforced_ones():
+    """tournament_k, elitism and population: the header's range is what the
+    library accepts, at both ends."""
+    assert _documented_range("tournament_k") == ("1", "population")
+    for P in (2, 50, 8192):
+        game.game_num_genes(game.config(population=P, tournament_k=P, elitism=1), 3)
+        game.game_num_genes(game.config(population=P, tournament_k=1, elitism=1), 3)
+        for k in (0, P + 1):
+            with pytest.raises(game.GameError):
+                game.game_num_genes(game.config(population=P, tournament_k=k, elitism=1), 3)
+    assert _documented_range("elitism") == ("0", "population-1")
+    game.game_num_genes(game.config(population=50, elitism=49), 3)
+    game.game_num_genes(game.config(population=50, elitism=0), 3)
+    with pytest.raises(game.GameError):
+        game.game_num_genes(game.config(population=50, elitism=50), 3)
+    assert re.search(r"int32_t\s+population;\s*/\*\s*P, 2\.\.8192", open(HEADER).read())
+    game.game_num_genes(game.config(population=8192, tournament_k=3), 3)
+    with pytest.raises(game.GameError):
+        game.game_num_genes(game.config(population=8193, tournament_k=3), 3)
 
 
 def test_tmse_threshold_range():
