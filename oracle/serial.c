@@ -8,8 +8,9 @@
  *   MSE = sum_k E_k / NP (Eq. 4), RMSE its root (Eq. 5), TMSE keeps E_k
  *   only where |t_k - Out| > R (Eq. 10; error_fn 3: where E_k > R).
  *
- * phi_{0,j} is T_j (Chebyshev), P_j (Legendre) or x^j (power) from the
- * three-term recurrences of Sec. 3; for the trigonometric expansion (Eq. 8)
+ * phi_{0,j} is T_j (Chebyshev), P_j (Legendre) or x^j (power), each from
+ * its textbook three-term recurrence (Eq. 1 leaves the function g free; the
+ * paper gives no recurrence); for the trigonometric expansion (Eq. 8)
  * phi_{0,j} = cos(j x) and phi_{1,j} = sin(j x).  Gene layout: gene 0 is a_0,
  * gene 1 + i*B*d + b*d + (j-1) multiplies phi_{b,j} of feature i.
  * Built with -ffp-contract=off: every product and sum is rounded on its own.

@@ -122,8 +122,11 @@ def test_error_functions(gg, error_fn):
     q = np.abs(r) if error_fn == 2 else r * r
     near = np.abs(q - R) <= 1e-5 * np.maximum(1.0, np.abs(q))
     budget = (near * (r * r)).sum(axis=0) / X.shape[0]
-    assert np.all(np.abs(f64 - ref) <= 1e-5 * ref + 1e-7 + budget)
-    assert np.all(f64 <= og.fitness(X, t, W, 0, 3) + 1e-6)
+    floor = 1e-7 * float(np.mean(t.astype(np.float64) ** 2))
+    assert np.all(np.abs(f64 - ref) <= 1e-5 * ref + floor + budget)
+    # thresholding only drops terms: never above the plain MSE (same tolerance)
+    mse = og.fitness(X, t, W, 0, 3)
+    assert np.all(f64 <= mse + 1e-5 * mse + floor)
 
 
 def test_nan_input_gives_infinite_error(gg):
@@ -181,3 +184,22 @@ def test_scale_workload_sampled(gg):
     idx = np.concatenate([idx, [0, prob.population - 1]])
     ref = og.fitness(prob.X, prob.t, W[idx], prob.basis, prob.degree)
     assert within(f64[idx], ref, prob.t).all(), np.max(np.abs(f64[idx] - ref) / ref)
+
+
+def test_precision_shape_fp32_sampled(gg):
+    """1,000,000 x 32, Chebyshev d=8 (257 genes), 4,096 chromosomes in one
+    float32 launch (the shape of the plain float32 reference run of the
+    time-to-target comparison): 32 chromosomes, among them the first and last
+    of the first and last 64-chromosome tiles, against the float64 oracle."""
+    prob = datagen.precision()
+    P = prob.population
+    W = datagen.random_genes(P, prob.n_genes, 14)
+    f32, f64 = gpu_fitness(gg, prob.basis, prob.degree, prob.X, prob.t, W)
+    rng = np.random.default_rng(1)
+    edges = [0, 63, P - 64, P - 1]
+    rest = rng.choice(np.setdiff1d(np.arange(P), edges), 28, replace=False)
+    idx = np.sort(np.concatenate([edges, rest]))
+    ref = og.fitness(prob.X, prob.t, W[idx], prob.basis, prob.degree)
+    ok = within(f64[idx], ref, prob.t)
+    assert ok.all(), np.max(np.abs(f64[idx] - ref) / ref)
+    assert np.array_equal(f32, f64.astype(np.float32))

@@ -4,7 +4,6 @@ Each test names what it pins.  None of them re-types the oracle's formula:
 they use closed forms, numpy library routines, the paper's worked example,
 special cases and invariants.
 """
-import math
 import os
 
 import numpy as np
@@ -82,47 +81,48 @@ def test_trig_cos_block_is_chebyshev_of_cos():
 
 
 # ------------------------------------------------------------- layout / model
+def _fourier_as_polynomial(X, G, d):
+    """Eq. 9's output written as a polynomial in z = exp(i f): a_j cos(j f) +
+    b_j sin(j f) is the real part of (a_j - i b_j) z^j, so the model is
+    a_0 + sum over features of Re(p(z)) with p(z) = sum_j (a_j - i b_j) z^j,
+    evaluated by numpy's polynomial routine.  [NP, P]."""
+    X = np.asarray(X, np.float64)
+    G = np.atleast_2d(np.asarray(G, np.float64))
+    z = np.exp(1j * X)                                   # [NP, N]
+    out = np.empty((X.shape[0], G.shape[0]))
+    for p in range(G.shape[0]):
+        coeffs = np.concatenate([[0.0], G[p, 1:d + 1] - 1j * G[p, d + 1:]])
+        out[:, p] = G[p, 0] + polynomial.polyval(z, coeffs).real.sum(axis=1)
+    return out
+
+
 def test_shared_gene_model_is_tied_per_feature_genes():
     """The paper's own polytrigo model shares a_j, b_j over all features
-    (Eq. 9; chromosome [a_0, a_1..a_d, b_1..b_d]).  Evaluated here by a plain
-    scalar loop with math.cos / math.sin, it must equal the per-feature model
+    (Eq. 9; chromosome [a_0, a_1..a_d, b_1..b_d]).  Written as a complex
+    polynomial in exp(i f), it must equal the per-feature model (recurrences)
     whose genes are tied across features."""
     rng = np.random.default_rng(4)
     N, d, NP = 4, 3, 7
     X = rng.uniform(-1, 1, (NP, N))
     shared = rng.uniform(-1, 1, 2 * d + 1)      # a_0, a_1..a_d, b_1..b_d
-    out_loop = []
-    for k in range(NP):
-        acc = shared[0]
-        for i in range(N):
-            for j in range(1, d + 1):
-                acc += shared[j] * math.cos(j * X[k, i]) + shared[j + d] * math.sin(j * X[k, i])
-        out_loop.append(acc)
+    ref = _fourier_as_polynomial(X, shared, d)[:, 0]
     tied = np.concatenate([[shared[0]]] + [shared[1:]] * N)
     out = game.outputs(X, tied, game.TRIG, d)[:, 0]
-    np.testing.assert_allclose(out, out_loop, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(out, ref, rtol=1e-13, atol=1e-13)
 
 
-def test_shared_trig_model_matches_the_scalar_loop_of_eq9():
+def test_shared_trig_model_matches_eq9_as_a_polynomial_in_exp_if():
     """The oracle's shared-gene outputs (sums computed once, then a product)
-    against a plain scalar loop over patterns, features and degrees with
-    math.cos / math.sin; and the same model written as the per-feature model
-    with tied genes."""
+    against Eq. 9 evaluated as a complex polynomial in exp(i f) per feature;
+    and the same model written as the per-feature model with tied genes."""
     rng = np.random.default_rng(8)
     N, d, NP, P = 5, 4, 9, 3
     X = rng.uniform(-3, 3, (NP, N))                   # raw radians, any range
     G = rng.uniform(-1, 1, (P, 2 * d + 1))
-    loop = np.empty((NP, P))
-    for k in range(NP):
-        for p in range(P):
-            acc = G[p, 0]
-            for i in range(N):
-                for j in range(1, d + 1):
-                    acc += G[p, j] * math.cos(j * X[k, i]) + G[p, d + j] * math.sin(j * X[k, i])
-            loop[k, p] = acc
-    np.testing.assert_allclose(game.shared_trig_outputs(X, G, d), loop, rtol=1e-12, atol=1e-12)
+    ref = _fourier_as_polynomial(X, G, d)
+    np.testing.assert_allclose(game.shared_trig_outputs(X, G, d), ref, rtol=1e-12, atol=1e-12)
     tied = np.concatenate([G[:, :1]] + [G[:, 1:]] * N, axis=1)
-    np.testing.assert_allclose(game.outputs(X, tied, game.TRIG, d), loop, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(game.outputs(X, tied, game.TRIG, d), ref, rtol=1e-12, atol=1e-12)
 
 
 def test_shared_trig_sums_closed_forms():
