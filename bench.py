@@ -120,19 +120,29 @@ def cpu_serial(prob, seconds=5.0):
                       f"({el / n:.2f} s each)"}
 
 
+def time_median(fn, stream, reps=25, warmup=3):
+    """Median duration (s) of `reps` calls of fn(), each bracketed by its own
+    pair of HIP events on `stream` (the stream the library queues on), after
+    `warmup` untimed calls."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(reps)]
+    for e0, e1 in pairs:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    pairs[-1][1].synchronize()
+    return float(np.median([e0.elapsed_time(e1) for e0, e1 in pairs])) / 1e3
+
+
 def time_fitness(gg, game, genes, n, reps, stream):
-    """Average duration (s) of one fitness launch (+ its finish kernel) on
-    the library's stream, timed with HIP events."""
+    """Median duration (s) of one fitness launch (plus its few-microsecond
+    finish kernel) on the library's stream, HIP events around each launch."""
     import torch
     f32 = torch.empty(n, dtype=torch.float32, device=genes.device)
-    gg.game_fitness(game.h, genes, n, f32)
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    for _ in range(reps):
-        gg.game_fitness(game.h, genes, n, f32)
-    end.record(stream)
-    end.synchronize()
-    return start.elapsed_time(end) / 1e3 / reps
+    return time_median(lambda: gg.game_fitness(game.h, genes, n, f32), stream, reps=max(20, reps))
 
 
 def time_steps(game, steps, warmup):
@@ -194,17 +204,28 @@ def form_bf16(gg, prob, steps, warmup):
                                            "float64 re-score on the GPU"}}
 
 
-def _run_to_target(gg, prob, precision, generations, target, surrogate=None, seed=0):
-    """One run from generation 0 on the precision problem, graph-captured,
-    stopping on the device once its best training error reaches `target`
-    (or after `generations` steps).  Wall time covers init, graph capture and
-    the whole run; the final best is re-scored in float64 on the training and
-    the validation set."""
+SURROGATE_CFG = dict(hidden=256, fp32_operands=0, archive=16384, minibatch=1024, train_steps=24,
+                     lr=1.5e-2, oversample=8, audit=64, rho_min=0.8, min_archive=4096, seed=0)
+
+
+def _run_to_target(gg, prob, precision, cap, val_target=None, train_target=None,
+                   surrogate=None, seed=0, chunk=5, split_at=None):
+    """One GA run on the precision problem from generation 0.
+
+    With val_target None the run takes exactly `cap` generations (the plain
+    float32 reference; with split_at it stops there once and resumes, so the
+    best training error at that generation is recorded on the way).  Else it
+    advances `chunk` generations at a time and after each chunk re-scores its
+    best chromosome (best by training error) in float64 on the validation
+    set, stopping once that is <= val_target or after `cap` generations.
+    Wall time covers initialisation, graph capture, the generations, the
+    surrogate's training and the validation checks.  The first time the
+    best training error is <= train_target is recorded too."""
     import torch
     dev = torch.device("cuda:0")
     P = prob.population
     cfg = gg.config(basis=prob.basis, degree=prob.degree, population=P, precision=precision,
-                    seed=seed, max_generations=generations, target=target)
+                    seed=seed, max_generations=cap, target=0.0)
     game = gg.Game(cfg, prob.X_dev, prob.t_dev)
     sur = None
     if surrogate is not None:
@@ -212,24 +233,54 @@ def _run_to_target(gg, prob, precision, generations, target, surrogate=None, see
         sur = gg.Surrogate(gg.surrogate_config(**surrogate), prob.n_genes,
                            surrogate["oversample"] * (P - cfg.elitism))
         gg.game_attach_surrogate(game.h, sur.h)
+
+    def val_of(best):
+        b = torch.from_numpy(best).to(dev).view(1, -1)
+        return float(game.rescore64(b, prob.Xv_dev, prob.tv_dev)[0])
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     game.init_population()
-    gens, best, err = game.run()
+    reached_val = reached_train = None
+    split = None
+    if val_target is None:
+        if split_at is not None:
+            g1, best1, err1 = game.run(max_generations=split_at)
+            split = {"generations": g1, "seconds": time.perf_counter() - t0,
+                     "train_mse_fp64": float(game.rescore64(
+                         torch.from_numpy(best1).to(dev).view(1, -1))[0])}
+        gens, best, err = game.run(max_generations=cap)
+    else:
+        gen = 0
+        while True:
+            gen = min(gen + chunk, cap)
+            gens, best, err = game.run(max_generations=gen)
+            if train_target is not None and reached_train is None and err <= train_target:
+                reached_train = {"generations": gens, "seconds": time.perf_counter() - t0}
+            if val_of(best) <= val_target:
+                reached_val = {"generations": gens, "seconds": time.perf_counter() - t0}
+                break
+            if gens >= cap:
+                break
     elapsed = time.perf_counter() - t0
     best_dev = torch.from_numpy(best).to(dev).view(1, -1)
     train64 = float(game.rescore64(best_dev)[0])
-    val64 = float(game.rescore64(best_dev, prob.Xv_dev, prob.tv_dev)[0])
-    # exact evaluations: the population each generation, plus the audited
-    # children when a surrogate screens
+    val64 = val_of(best)
+    # exact evaluations: the population each generation (generation 0
+    # included), plus the audited children when a surrogate screens
     per_gen = P + (surrogate["audit"] if surrogate is not None else 0)
-    res = {"generations": gens, "seconds": elapsed, "reached": bool(train64 <= target * (1 + 1e-3)),
-           "train_mse_fp64": train64, "validation_mse_fp64": val64,
-           "exact_evaluations": int(gens) * per_gen,
+    res = {"generations": gens, "seconds": elapsed, "train_mse_fp64": train64,
+           "validation_mse_fp64": val64, "exact_evaluations": (int(gens) + 1) * per_gen,
            "ms_per_generation": elapsed * 1e3 / max(gens, 1)}
+    if val_target is not None:
+        res["reached"] = reached_val is not None
+        res["reached_train_target"] = reached_train
+    if split is not None:
+        res["at_split"] = split
     if sur is not None:
         st = sur.stats()
         res["surrogate"] = {"last_rho": st["rho"], "screened_generations": st["screened_total"],
+                            "screened_fraction": st["screened_total"] / max(gens, 1),
                             "adam_steps": st["adam_steps"]}
         sur.close()
     game.close()
@@ -260,69 +311,107 @@ def _rho_trace(gg, prob, generations, surrogate):
     return trace
 
 
-def form_time_to_target(gg, prob, plain_generations=300, cap=3, seeds=(0, 1, 2, 3, 4)):
-    """Time to a training-error target on the precision problem, per GA seed:
-    plain FP32 GAME defines the target (its float64 best error after
-    `plain_generations` generations); plain BF16 and the surrogate-screened
-    BF16 form (network 257-256-256-1, 8x oversampled offspring, exact
-    fallback below rank correlation 0.8) run with the same seed until they
-    reach it, at most `cap` times as many generations.  Medians over the
-    seeds are reported.  For the first seed the surrogate run's audit
-    correlation is traced, and an untrained, always-trusted network is run
-    as the ablation.  Validation error of every final best is reported
-    beside it."""
-    sur_cfg = dict(hidden=256, fp32_operands=0, archive=16384, minibatch=1024, train_steps=24,
-                   lr=1.5e-2, oversample=8, audit=64, rho_min=0.8, min_archive=4096, seed=0)
+def form_time_to_target(gg, prob, reference_generations=1000, secondary_generations=300, cap=3,
+                        seeds=(0, 1, 2, 3, 4), surrogate_cfg=None):
+    """Time to a validation-error target on the precision problem, per GA
+    seed.  Plain float32 GAME runs `reference_generations` generations; the
+    float64 validation error of its best chromosome is the target T*.  Plain
+    BF16 and the surrogate-screened BF16 form (network 257-256-256-1, 8x
+    oversampled offspring, exact fallback below rank correlation 0.8) run
+    with the same seed until the float64 validation error of their best
+    chromosome is <= T* (checked every 5 generations), at most `cap` times as
+    many generations.  Medians over the seeds are reported.  Secondary line:
+    the earlier target, the plain float32 best training error after
+    `secondary_generations` generations, reached by the other two forms on
+    their way.  For the first seed the surrogate run's audit correlation is
+    traced, and an untrained, always-trusted network is run as the
+    ablation."""
+    sur_cfg = dict(surrogate_cfg or SURROGATE_CFG)
     per_seed = []
     first = None
     for seed in seeds:
-        log(f"time to target: seed {seed}")
-        plain = _run_to_target(gg, prob, gg.GAME_FP32, plain_generations, 0.0, seed=seed)
-        target = plain["train_mse_fp64"]
-        plain["reached"] = True
-        bf16 = _run_to_target(gg, prob, gg.GAME_BF16, cap * plain_generations, target, seed=seed)
-        chosen = _run_to_target(gg, prob, gg.GAME_BF16, cap * plain_generations, target, sur_cfg,
-                                seed=seed)
-        per_seed.append({"seed": seed, "target_train_mse": target,
+        log(f"time to target: seed {seed}, plain FP32 reference")
+        plain = _run_to_target(gg, prob, gg.GAME_FP32, reference_generations, seed=seed,
+                               split_at=secondary_generations)
+        T = plain["validation_mse_fp64"]
+        T2 = plain["at_split"]["train_mse_fp64"]
+        log(f"time to target: seed {seed}, T* = {T:.5f}; plain BF16, surrogate + BF16")
+        cap_g = cap * reference_generations
+        bf16 = _run_to_target(gg, prob, gg.GAME_BF16, cap_g, val_target=T, train_target=T2,
+                              seed=seed)
+        chosen = _run_to_target(gg, prob, gg.GAME_BF16, cap_g, val_target=T, train_target=T2,
+                                surrogate=sur_cfg, seed=seed)
+        per_seed.append({"seed": seed, "target_validation_mse": T,
+                         "secondary_target_train_mse": T2,
                          "plain_fp32": plain, "plain_bf16": bf16, "surrogate_bf16": chosen})
         if first is None:
             first = per_seed[-1]
+            log("time to target: rho trace and untrained-network ablation")
             chosen["rho_trace"] = _rho_trace(gg, prob, chosen["generations"], sur_cfg)
             # Ablation: the same screening with a network that is never
             # trained and always trusted (offspring picked by random-weight
             # predictions).
             untrained_cfg = dict(sur_cfg, train_steps=0, rho_min=-1.0, min_archive=0)
             first["untrained_surrogate_bf16"] = _run_to_target(
-                gg, prob, gg.GAME_BF16, cap * plain_generations, target, untrained_cfg, seed=seed)
+                gg, prob, gg.GAME_BF16, cap_g, val_target=T, train_target=T2,
+                surrogate=untrained_cfg, seed=seed)
 
-    def med(run, key):
-        return float(np.median([r[run][key] for r in per_seed]))
+    def med(vals):
+        vals = [v for v in vals if v is not None]
+        return float(np.median(vals)) if vals else None
 
-    median = {run: {"seconds": med(run, "seconds"), "generations": med(run, "generations"),
-                    "validation_mse_fp64": med(run, "validation_mse_fp64"),
-                    "reached": sum(bool(r[run]["reached"]) for r in per_seed)}
-              for run in ("plain_fp32", "plain_bf16", "surrogate_bf16")}
-    speedups = [r["plain_fp32"]["seconds"] / r["surrogate_bf16"]["seconds"] for r in per_seed
-                if r["surrogate_bf16"]["reached"]]
+    def primary(r, run):
+        return r[run]["seconds"] if run == "plain_fp32" else (
+            r[run]["seconds"] if r[run]["reached"] else None)
+
+    median = {"plain_fp32": {"seconds": med([r["plain_fp32"]["seconds"] for r in per_seed]),
+                             "generations": med([r["plain_fp32"]["generations"] for r in per_seed]),
+                             "validation_mse_fp64": med([r["plain_fp32"]["validation_mse_fp64"]
+                                                         for r in per_seed])}}
+    for run in ("plain_bf16", "surrogate_bf16"):
+        rs = [r[run] for r in per_seed]
+        median[run] = {"seconds": med([x["seconds"] if x["reached"] else None for x in rs]),
+                       "generations": med([x["generations"] if x["reached"] else None for x in rs]),
+                       "validation_mse_fp64": med([x["validation_mse_fp64"] for x in rs]),
+                       "reached": sum(bool(x["reached"]) for x in rs)}
+    speed = [r["plain_fp32"]["seconds"] / r["surrogate_bf16"]["seconds"] for r in per_seed
+             if r["surrogate_bf16"]["reached"]]
     vs_bf16 = [r["plain_bf16"]["seconds"] / r["surrogate_bf16"]["seconds"] for r in per_seed
                if r["surrogate_bf16"]["reached"] and r["plain_bf16"]["reached"]]
+    # secondary: the 300-generation training target
+    sec = {}
+    for run in ("plain_bf16", "surrogate_bf16"):
+        hit = [r[run]["reached_train_target"] for r in per_seed]
+        sec[run] = {"seconds": med([h["seconds"] if h else None for h in hit]),
+                    "generations": med([h["generations"] if h else None for h in hit]),
+                    "reached": sum(h is not None for h in hit)}
+    sec["plain_fp32"] = {"seconds": med([r["plain_fp32"]["at_split"]["seconds"] for r in per_seed]),
+                         "generations": secondary_generations, "reached": len(per_seed)}
+    s_speed = [r["plain_fp32"]["at_split"]["seconds"] / r["surrogate_bf16"]["reached_train_target"]["seconds"]
+               for r in per_seed if r["surrogate_bf16"]["reached_train_target"]]
+    sec["speedup_chosen_vs_plain_fp32_median"] = med(s_speed)
     out = {"workload": "precision problem (1,000,000 x 32, Chebyshev degree 8, population "
                        "4,096, validation 250,000 patterns), GA seeds "
-                       f"{list(seeds)}; target = plain FP32 best training error after "
-                       f"{plain_generations} generations, per seed",
+                       f"{list(seeds)}; target T* = float64 validation error of plain FP32's "
+                       f"best after {reference_generations} generations, per seed; the other "
+                       "forms stop once their best's float64 validation error is <= T* "
+                       f"(checked every 5 generations, at most {cap_g} generations)",
            "median": median,
-           "speedup_chosen_vs_plain_fp32_median": float(np.median(speedups)) if speedups else None,
-           "speedup_chosen_vs_plain_bf16_median": float(np.median(vs_bf16)) if vs_bf16 else None,
-           "seeds": [{"seed": r["seed"], "target_train_mse": r["target_train_mse"],
-                      **{run: {k: r[run][k] for k in ("generations", "seconds", "reached",
-                                                      "validation_mse_fp64")}
-                         for run in ("plain_fp32", "plain_bf16", "surrogate_bf16")}}
+           "speedup_chosen_vs_plain_fp32_median": med(speed),
+           "speedup_chosen_vs_plain_bf16_median": med(vs_bf16),
+           "chosen_beats_plain_fp32": bool(speed) and med(speed) > 1.0,
+           "secondary_300_generation_training_target": sec,
+           "seeds": [{"seed": r["seed"], "target_validation_mse": r["target_validation_mse"],
+                      **{run: {k: r[run].get(k) for k in ("generations", "seconds", "reached",
+                                                          "validation_mse_fp64")}
+                         for run in ("plain_fp32", "plain_bf16", "surrogate_bf16")},
+                      "surrogate": r["surrogate_bf16"].get("surrogate")}
                      for r in per_seed],
            "surrogate_config": sur_cfg}
     # the first seed in full: runs, surrogate statistics, rho trace, ablation
-    out.update({"target_train_mse": first["target_train_mse"], "plain_fp32": first["plain_fp32"],
-                "plain_bf16": first["plain_bf16"], "surrogate_bf16": first["surrogate_bf16"],
-                "untrained_surrogate_bf16": first["untrained_surrogate_bf16"]})
+    out.update({"first_seed": {k: first[k] for k in (
+        "target_validation_mse", "secondary_target_train_mse", "plain_fp32", "plain_bf16",
+        "surrogate_bf16", "untrained_surrogate_bf16")}})
     return out
 
 
@@ -408,8 +497,9 @@ def form_batched(gg, steps, warmup):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     n_items, tiles, grid = batch.items()
+    # the tuned decomposition's evaluation launch alone, median of 25
+    t_kernel = time_median(batch.evaluate, torch.cuda.current_stream(), reps=25)
     batch.close()
-    t_kernel = tune["ms"] / 1e3
     achieved = flops / t_kernel / 1e12
     return {"workload": "batched: 256 independent runs, patterns 1e3-2e5 log-uniform, features "
                         "4-64, degree 2-10, population 32-1024, Chebyshev/power, FP32 "
@@ -421,7 +511,40 @@ def form_batched(gg, steps, warmup):
                          "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
                          "traffic": profiled_traffic("fitness_batch_256runs.md"), "kernel_ms": t_kernel * 1e3, "flops_per_launch": flops},
             "autotune": {"tiles_per_item": tiles, "grid": grid, "items": n_items,
-                         "times_ms": tune["times_ms"]}}
+                         "best_mean_ms": tune["ms"], "times_ms": tune["times_ms"]}}
+
+
+def scale_step(gg, prob, steps, warmup):
+    """The headline line: generations of the scale workload, and its fused
+    fitness kernel on the MFMA roofline."""
+    import torch
+    P = prob.population
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(prob.X).to(dev)
+    t = torch.from_numpy(prob.t).to(dev)
+    cfg = gg.config(basis=prob.basis, degree=prob.degree, population=P, tournament_k=3,
+                    elitism=2, p_crossover=0.9, p_mutation=0.05, sigma_mutation=0.1, seed=0,
+                    max_generations=1 << 30, target=-1.0)
+    game = gg.Game(cfg, X, t)
+    game.init_population()
+    stream = torch.cuda.current_stream()
+    log("scale workload: timing generations")
+    elapsed = time_steps(game, steps, warmup)
+    st = game.state()
+    assert st["stopped"] == 0, "the run stopped inside the timed region"
+    # Dominant kernel: the fused fitness launch (plus its tiny finish kernel)
+    # on the same stream and launch configuration, median of HIP-event-timed
+    # launches.
+    pop, _ = game.population()
+    t_kernel = time_fitness(gg, game, pop, P, 25, stream)
+    game.close()
+    flops = 2.0 * (prob.n_genes - 1) * P * prob.n_patterns
+    achieved = flops / t_kernel / 1e12
+    return elapsed, {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                     "traffic": profiled_traffic("fitness_f32_scale.md"),
+                     "kernel_ms": t_kernel * 1e3, "kernel_timing": "median of 25 launches",
+                     "flops_per_launch": flops}
 
 
 def main():
@@ -436,8 +559,12 @@ def main():
                     help="skip the paper-shaped scaling table (shared-gene polytrigo runs)")
     ap.add_argument("--no-target", action="store_true",
                     help="skip the time-to-target comparison (plain FP32 vs surrogate + BF16)")
-    ap.add_argument("--target-generations", type=int, default=300,
+    ap.add_argument("--target-generations", type=int, default=1000,
                     help="generations of the plain FP32 run that sets the time-to-target goal")
+    ap.add_argument("--target-seeds", type=int, default=5,
+                    help="GA seeds of the time-to-target comparison (0, 1, ...)")
+    ap.add_argument("--only", choices=["scale", "bf16", "batched", "target", "paper"],
+                    help="run one workload alone and print its result (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise kernel of known traffic (256 MiB read, "
                          "256 MiB written per launch) to scale hardware byte counters")
@@ -461,44 +588,35 @@ def main():
     from paper_1304_0597_amd import game as gg
 
     gg.lib()
+    seeds = tuple(range(args.target_seeds))
+    if args.only in ("bf16", "batched", "target", "paper"):
+        if args.only == "bf16":
+            log("precision form: building inputs")
+            res = form_bf16(gg, precision_problem(), args.steps, args.warmup)
+        elif args.only == "batched":
+            log("batched form: building inputs, autotuning, timing")
+            res = form_batched(gg, args.steps, args.warmup)
+        elif args.only == "target":
+            log("time to target: building inputs")
+            res = form_time_to_target(gg, precision_problem(), args.target_generations,
+                                      seeds=seeds)
+        else:
+            res = form_paper_shaped(gg)
+        print(json.dumps({"only": args.only, "result": res}), flush=True)
+        return
+
     log("scale workload: building inputs")
     prob = datagen.scale()
     P = prob.population
-    dev = torch.device("cuda:0")
-    X = torch.from_numpy(prob.X).to(dev)
-    t = torch.from_numpy(prob.t).to(dev)
-    cfg = gg.config(basis=prob.basis, degree=prob.degree, population=P, tournament_k=3,
-                    elitism=2, p_crossover=0.9, p_mutation=0.05, sigma_mutation=0.1, seed=0,
-                    max_generations=1 << 30, target=-1.0)
-    game = gg.Game(cfg, X, t)
-    game.init_population()
-    stream = torch.cuda.current_stream()
-
-    log("scale workload: timing generations")
-    elapsed = time_steps(game, args.steps, args.warmup)
-    st = game.state()
-    assert st["stopped"] == 0, "the run stopped inside the timed region"
-    ms_per_step = elapsed * 1e3 / args.steps
-    evals = P * prob.n_patterns * args.steps
-    value = evals / elapsed
-
-    # Dominant kernel: the fused fitness launch (plus its tiny finish kernel)
-    # on the same stream and launch configuration, timed with HIP events.
-    pop, _ = game.population()
-    t_kernel = time_fitness(gg, game, pop, P, max(10, args.steps), stream)
-    Kf = prob.n_genes - 1
-    flops = 2.0 * Kf * P * prob.n_patterns
-    achieved = flops / t_kernel / 1e12
-    traffic = profiled_traffic("fitness_f32_scale.md")
-
+    elapsed, roofline = scale_step(gg, prob, args.steps, args.warmup)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": P * prob.n_patterns * args.steps / elapsed,
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": elapsed * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -509,12 +627,11 @@ def main():
                    "n_patterns": prob.n_patterns, "n_features": prob.n_features,
                    "degree": prob.degree, "basis": "legendre", "population": P,
                    "genes": prob.n_genes},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-                     "traffic": traffic, "kernel_ms": t_kernel * 1e3,
-                     "flops_per_launch": flops},
+        "roofline": roofline,
     }
-    game.close()
+    if args.only == "scale":
+        print(json.dumps(out), flush=True)
+        return
     if not args.no_forms:
         log("precision form: building inputs")
         pprob = precision_problem()
@@ -528,7 +645,8 @@ def main():
             out["paper_shaped"] = form_paper_shaped(gg)
         if not args.no_target:
             log("time to target: plain FP32, plain BF16, surrogate + BF16")
-            out["time_to_target"] = form_time_to_target(gg, pprob, args.target_generations)
+            out["time_to_target"] = form_time_to_target(gg, pprob, args.target_generations,
+                                                        seeds=seeds)
         del pprob
     if not args.no_cpu:
         log("oracle on the host cores")
