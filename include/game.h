@@ -254,6 +254,21 @@ int game_ga_next(const game_config* cfg, int32_t n_genes, const float* pop_dev,
                  const float* fitness_dev, int32_t generation, float* out_dev,
                  void* workspace_dev, size_t workspace_bytes, void* hip_stream);
 
+/* game_ga_next for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same genetic step with the same results bit for bit, but its rank
+ * order and roulette sums live in a fixed scratch array inside the library
+ * (98,304 bytes on each device that runs it, held until the process ends)
+ * instead of a caller workspace, and it allocates nothing.  Arguments as in
+ * game_ga_next without the workspace; population up to 8192 (a larger one
+ * is GAME_EINVAL).  All calls on one device share that device's scratch and
+ * nothing in it carries over between calls: calls that overlap on one
+ * device (several streams or host threads) race, so the caller orders them.
+ * Runs on the current device, which must be the stream's. */
+int game_ga_next_static(const game_config* cfg, int32_t n_genes, const float* pop_dev,
+                        const float* fitness_dev, int32_t generation, float* out_dev,
+                        void* hip_stream);
+
 /* Stateless generation-0 population [P x n_genes] (cfg.init_mode, cfg.seed). */
 int game_init_genes(const game_config* cfg, int32_t n_genes, float* out_dev, void* hip_stream);
 

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -704,8 +705,8 @@ int game_rescore64(game_t h, const float* X, const float* t, int64_t NP, const f
 
 namespace {
 
-int predict_common(game_t h, const float* X, const float* t, int64_t NP, const float* genes,
-                   int32_t n, float threshold, float* out, int64_t* counts) {
+static int predict_common(game_t h, const float* X, const float* t, int64_t NP, const float* genes,
+                          int32_t n, float threshold, float* out, int64_t* counts) {
   if (!h) return fail(GAME_EINVAL, "handle is NULL");
   if (!genes || (!out && !counts)) return fail(GAME_EINVAL, "NULL argument");
   if (counts && ((X == nullptr) != (t == nullptr)))
@@ -942,20 +943,12 @@ size_t game_ga_workspace_size(const game_config* c) {
          align_up((size_t)c->population * sizeof(double));
 }
 
-int game_ga_next(const game_config* c, int32_t K, const float* pop, const float* fitness,
-                 int32_t generation, float* out, void* ws, size_t ws_bytes, void* stream) {
-  int rc = check_config(c, 1);
-  if (rc) return rc;
-  if (K < 2 || K > kMaxGenes) return fail(GAME_EINVAL, "n_genes %d not in 2..%d", K, kMaxGenes);
-  if (!pop || !fitness || !out) return fail(GAME_EINVAL, "NULL argument");
-  if (generation < 1) return fail(GAME_EINVAL, "generation %d < 1", generation);
-  const size_t need = game_ga_workspace_size(c);
-  if (!ws || !aligned(ws, kAlign) || ws_bytes < need)
-    return fail(GAME_EWORKSPACE, "workspace must be 256-byte aligned with %zu bytes", need);
-  const size_t bytes = (size_t)c->population * K * sizeof(float);
-  if ((const char*)out < (const char*)pop + bytes && (const char*)pop < (const char*)out + bytes)
-    return fail(GAME_EINVAL, "out overlaps pop");
-  hipStream_t s = (hipStream_t)stream;
+namespace {
+
+// The genetic step after validation: rank order and roulette sums in `ws`
+// (game_ga_workspace_size bytes), then the next generation.
+static int ga_next_on(const game_config* c, int32_t K, const float* pop, const float* fitness,
+               int32_t generation, float* out, void* ws, hipStream_t s) {
   int32_t* order = (int32_t*)ws;
   double* cum = (double*)((char*)ws + align_up((size_t)c->population * sizeof(int32_t)));
   GAME_HIP(launch_rank(fitness, c->population, order, s));
@@ -970,6 +963,83 @@ int game_ga_next(const game_config* c, int32_t K, const float* pop, const float*
   ga.generation = generation;
   GAME_HIP(launch_ga_next(ga, s));
   return GAME_OK;
+}
+
+static int check_ga_next(const game_config* c, int32_t K, const float* pop, const float* fitness,
+                  int32_t generation, const float* out) {
+  int rc = check_config(c, 1);
+  if (rc) return rc;
+  if (K < 2 || K > kMaxGenes) return fail(GAME_EINVAL, "n_genes %d not in 2..%d", K, kMaxGenes);
+  if (!pop || !fitness || !out) return fail(GAME_EINVAL, "NULL argument");
+  if (generation < 1) return fail(GAME_EINVAL, "generation %d < 1", generation);
+  const size_t bytes = (size_t)c->population * K * sizeof(float);
+  if ((const char*)out < (const char*)pop + bytes && (const char*)pop < (const char*)out + bytes)
+    return fail(GAME_EINVAL, "out overlaps pop");
+  return GAME_OK;
+}
+
+}  // namespace
+
+int game_ga_next(const game_config* c, int32_t K, const float* pop, const float* fitness,
+                 int32_t generation, float* out, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_ga_next(c, K, pop, fitness, generation, out);
+  if (rc) return rc;
+  const size_t need = game_ga_workspace_size(c);
+  if (!ws || !aligned(ws, kAlign) || ws_bytes < need)
+    return fail(GAME_EWORKSPACE, "workspace must be 256-byte aligned with %zu bytes", need);
+  return ga_next_on(c, K, pop, fitness, generation, out, ws, (hipStream_t)stream);
+}
+
+// ------------------------------------------------ fixed-scratch genetic step
+// The scratch of game_ga_next_static: room for the rank order and the
+// roulette sums of the largest population, laid out as game_ga_next lays
+// out its workspace.  Each device holds its own copy until the process
+// ends.  Host code never passes the array's name to a kernel or a copy (on
+// the host it is only a stand-in for the symbol): it uses the device
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes =
+    ((size_t)kMaxPopulation * sizeof(int32_t) + kAlign - 1) / kAlign * kAlign +
+    (size_t)kMaxPopulation * sizeof(double);
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxScratchDevices];  // address of `scratch` on each device, once looked up
+
+// Device address of the current device's scratch, looked up on its first use.
+static int current_scratch(void** out) {
+  int dev = 0;
+  GAME_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(GAME_EINVAL, "device %d: the fixed scratch serves devices 0..%d", dev,
+                kMaxScratchDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    GAME_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(GAME_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return GAME_OK;
+}
+
+}  // namespace
+
+int game_ga_next_static(const game_config* c, int32_t K, const float* pop, const float* fitness,
+                        int32_t generation, float* out, void* stream) {
+  int rc = check_ga_next(c, K, pop, fitness, generation, out);
+  if (rc) return rc;
+  const size_t need = game_ga_workspace_size(c);
+  if (need > kStaticScratchBytes)
+    return fail(GAME_EINVAL, "population %d needs %zu scratch bytes; the fixed scratch holds %zu",
+                c->population, need, kStaticScratchBytes);
+  void* ws = nullptr;
+  rc = current_scratch(&ws);
+  if (rc) return rc;
+  return ga_next_on(c, K, pop, fitness, generation, out, ws, (hipStream_t)stream);
 }
 
 int game_init_genes(const game_config* c, int32_t K, float* out, void* stream) {

@@ -82,6 +82,8 @@ _SIGS = {
     "game_ga_workspace_size": (c_size_t, [POINTER(game_config)]),
     "game_ga_next": (c_int32, [POINTER(game_config), c_int32, c_void_p, c_void_p, c_int32,
                                c_void_p, c_void_p, c_size_t, c_void_p]),
+    "game_ga_next_static": (c_int32, [POINTER(game_config), c_int32, c_void_p, c_void_p, c_int32,
+                                      c_void_p, c_void_p]),
     "game_init_genes": (c_int32, [POINTER(game_config), c_int32, c_void_p, c_void_p]),
     "game_last_error": (ctypes.c_char_p, []),
     "game_surrogate_config_default": (c_int32, [POINTER(game_surrogate_config)]),
@@ -402,6 +404,16 @@ def game_ga_next(cfg, n_genes, pop, fitness, generation, out, workspace, stream=
                               _ptr(fitness, torch.float32), generation, _ptr(out, torch.float32),
                               _ptr(workspace), workspace.numel() * workspace.element_size(),
                               _stream(stream)))
+
+
+def game_ga_next_static(cfg, n_genes, pop, fitness, generation, out, stream=None) -> None:
+    import torch
+    _shape(pop, (cfg.population, n_genes), "pop")
+    _shape(fitness, (cfg.population,), "fitness")
+    _shape(out, (cfg.population, n_genes), "out")
+    _check(lib().game_ga_next_static(ctypes.byref(cfg), n_genes, _ptr(pop, torch.float32),
+                                     _ptr(fitness, torch.float32), generation,
+                                     _ptr(out, torch.float32), _stream(stream)))
 
 
 def game_init_genes(cfg, n_genes, out, stream=None) -> None:
