@@ -21,11 +21,11 @@ namespace game {
 
 namespace {
 
-// The single-run float32 body for one item of run `run`, with the run's
-// expansion family and degree read at run time: one body serves every run,
-// so the kernel makes no calls (a call per item would save and restore the
-// callee's registers in private memory every time) and has the register
-// allocation of one body.
+// The single-run float32 body for one item of run `run`, at the run's
+// degree (a uniform switch over the 16 compile-time degrees, all inlined)
+// with the run's expansion family read at run time: the kernel makes no
+// calls (a call per item would save and restore the callee's registers in
+// private memory every time).
 __device__ __forceinline__ void item_body(const BatchRun* __restrict__ run, const float* genes,
                                           int split, int ctile, float* lds) {
   FitArgs fa{};
@@ -49,7 +49,17 @@ __device__ __forceinline__ void item_body(const BatchRun* __restrict__ run, cons
   fa.R = run->R;
   fa.degree = run->D;
   fa.basis = run->basis;
-  fitness_f32_block<-1, 0>(fa, genes, split, ctile, lds);
+  switch (__builtin_amdgcn_readfirstlane(run->D)) {
+#define GAME_CASE(D) \
+  case D:            \
+    fitness_f32_block<-1, D>(fa, genes, split, ctile, lds); \
+    break;
+    GAME_CASE(1) GAME_CASE(2) GAME_CASE(3) GAME_CASE(4) GAME_CASE(5) GAME_CASE(6)
+    GAME_CASE(7) GAME_CASE(8) GAME_CASE(9) GAME_CASE(10) GAME_CASE(11) GAME_CASE(12)
+    GAME_CASE(13) GAME_CASE(14) GAME_CASE(15) GAME_CASE(16)
+#undef GAME_CASE
+    default: break;
+  }
 }
 
 }  // namespace

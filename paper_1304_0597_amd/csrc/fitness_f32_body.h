@@ -45,11 +45,11 @@ __device__ __forceinline__ gptr_f32 global_f32(const float* p) { return (gptr_f3
 // Tile range [split's tiles] x chromosome tile ctile of the launch described
 // by a_in; writes a.partial[split * ld_partial + chromosome].  genes: the
 // chromosomes being scored; lds: the workgroup's dynamic LDS.  D is the
-// degree, or 0 for the degree a_in.degree read at run time: the same
-// K-steps in the same order with the same recurrence arithmetic, so both
-// forms give the same bits (the batched kernel runs every run's degree
-// through one body this way).  BASIS is the expansion family, or -1 for the
-// family a_in.basis read at run time, likewise.
+// degree.  BASIS is the expansion family, or -1 for the family a_in.basis
+// read at run time: the same K-steps in the same order, each recurrence step
+// the table-driven form of Recur<-1> with the bits of the fixed family's, so
+// both forms give the same bits (the batched kernel runs every run's family
+// through one body per degree this way).
 template <int BASIS, int D>
 __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const float* __restrict__ genes,
                                                   int split, int ctile, float* lds) {
@@ -73,7 +73,8 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   a.n_tiles = uniform(a_in.n_tiles);
   a.error_fn = uniform(a_in.error_fn);
   a.R = uniform(a_in.R);
-  const int Dv = D > 0 ? D : uniform(a_in.degree);
+  static_assert(D >= 1 && D <= kMaxDegree, "compile-time degree");
+  constexpr int Dv = D;
   const int fam = BASIS >= 0 ? BASIS : uniform(a_in.basis);
   const bool trig = fam == 3;
   genes = uniform(genes);
@@ -200,9 +201,11 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
         if (q + 1 < a.Q) load_x(row0, q + 1, xn);
         else if (tile + 1 < tile_end) load_x(row0 + kTileRows, 0, xn);
         Recur<BASIS> rc[2];
-        if constexpr (BASIS < 0) rc[0].fam = rc[1].fam = fam;
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) rc[rb].seed(x[rb], h);
+        for (int rb = 0; rb < 2; ++rb) {
+          if constexpr (BASIS < 0) rc[rb].seed(fam, x[rb], h);
+          else rc[rb].seed(x[rb], h);
+        }
         const float* wl = wbuf + m * WS + (2 * (q - q_begin) + h) * Dv;
         // One K-step per degree: two MFMA columns x two row blocks, then the
         // recurrence moves every lane's A value to the next degree.
@@ -213,30 +216,20 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
             acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(rc[rb].cur, b1, acc[rb][1], 0, 0, 0);
           }
         };
-        if constexpr (D > 0) {
-          auto kstep = [&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            mfma4(wl[j], wl[32 * WS + j]);
-            if constexpr (j + 1 < D) {
+        auto kstep = [&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          mfma4(wl[j], wl[32 * WS + j]);
+          if constexpr (j + 1 < D) {
 #pragma unroll
-              for (int rb = 0; rb < 2; ++rb) rc[rb].template advance<j + 1>(x[rb]);
+            for (int rb = 0; rb < 2; ++rb) {
+              if constexpr (BASIS < 0) rc[rb].template advance_fam<j + 1>(fam);
+              else rc[rb].template advance<j + 1>(x[rb]);
             }
-          };
-          [&]<int... J>(std::integer_sequence<int, J...>) {
-            (kstep(std::integral_constant<int, J>{}), ...);
-          }(std::make_integer_sequence<int, D>{});
-        } else {
-          float b0 = wl[0], b1 = wl[32 * WS];
-          for (int j = 0; j + 1 < Dv; ++j) {
-            const float n0 = wl[j + 1], n1 = wl[32 * WS + j + 1];
-            mfma4(b0, b1);
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb) rc[rb].advance_rt(j + 1, x[rb]);
-            b0 = n0;
-            b1 = n1;
           }
-          mfma4(b0, b1);
-        }
+        };
+        [&]<int... J>(std::integer_sequence<int, J...>) {
+          (kstep(std::integral_constant<int, J>{}), ...);
+        }(std::make_integer_sequence<int, D>{});
       }
     }
 
