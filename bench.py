@@ -428,44 +428,106 @@ def form_paper_shaped(gg, generations=4000):
     model (2d+1 genes, Eq. 9) of degree 1, 2, 4 and 8 on the 2,100 x 11
     binary set replicated to 0.15, 16, 128 and 512 MB of the paper's data
     size, 23 chromosomes, tournament 4, crossover 0.9, mutation 0.2,
-    elitism 2, TMSE R = 0.49, 4,000 generations.  One run = the cos/sin sums
-    computed once, initialisation and the graph-captured training loop, with
-    the data already in GPU memory."""
+    elitism 2, TMSE R = 0.49, 4,000 generations.
+
+    Each row is split into Table 3's columns (Eqs. 11-13): HtoD is the upload
+    of the replicated patterns and targets from host memory; DP the device
+    time of the run (HIP events around the cos/sin sums, initialisation and
+    the graph-captured training loop on the stream); HP the host time of the
+    run not covered by device time (wall clock minus DP); DtoH the copy of
+    the final population and its errors back to the host; DtoD is zero (the
+    loop copies nothing on the device: populations alternate between two
+    buffers).  P = DP + HP, T = HtoD + DtoH + DtoD, TOT = P + T."""
     import torch
     from paper_1304_0597_amd import datagen
     base = datagen.paper_shaped()
     dev = torch.device("cuda:0")
-    Xb = torch.from_numpy(base.X).to(dev)
-    tb = torch.from_numpy(base.t).to(dev)
+    stream = torch.cuda.current_stream()
     rows = {}
     for d, paper in PAPER_TABLE3_TOT.items():
         for size, tot in zip(datagen.PAPER_SIZES_MB, paper):
             n = datagen.paper_rows(size)
             reps = -(-n // base.n_patterns)
-            X = Xb.repeat(reps, 1)[:n].contiguous()
-            t = tb.repeat(reps)[:n].contiguous()
+            Xh = np.ascontiguousarray(np.tile(base.X, (reps, 1))[:n])
+            th = np.ascontiguousarray(np.tile(base.t, reps)[:n])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X = torch.from_numpy(Xh).to(dev)
+            t = torch.from_numpy(th).to(dev)
+            torch.cuda.synchronize()
+            htod = time.perf_counter() - t0
             Z = torch.empty((n, 2 * d), dtype=torch.float32, device=dev)
             cfg = gg.config(basis=gg.GAME_POWER, degree=1, population=23, tournament_k=4,
                             elitism=2, p_crossover=0.9, p_mutation=0.2, sigma_mutation=0.1,
                             error_fn=gg.GAME_TMSE, tmse_R=0.49, seed=0,
                             max_generations=generations, target=0.0)
             game = gg.Game(cfg, Z, t)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            gg.game_trig_sums(X, d, Z, torch.cuda.current_stream())
+            t1 = time.perf_counter()
+            e0.record(stream)
+            gg.game_trig_sums(X, d, Z, stream)
             game.init_population()
             gens, _, err = game.run()
-            elapsed = time.perf_counter() - t0
+            e1.record(stream)
+            e1.synchronize()
+            wall = time.perf_counter() - t1
+            dp = e0.elapsed_time(e1) / 1e3
+            hp = max(0.0, wall - dp)
+            t2 = time.perf_counter()
+            pop, fit = game.population()
+            pop_h, fit_h = pop.cpu(), fit.cpu()
+            dtoh = time.perf_counter() - t2
             game.close()
-            rows[f"d{d}_{size:g}MB"] = {"patterns": n, "seconds": elapsed, "generations": gens,
-                                        "best_tmse": err, "paper_tot_seconds": tot,
-                                        "ratio_paper_over_this": tot / elapsed}
-            del X, t, Z
+            P_ = dp + hp
+            T_ = htod + dtoh
+            rows[f"d{d}_{size:g}MB"] = {
+                "patterns": n, "generations": gens, "best_tmse": err,
+                "seconds": P_ + T_,
+                "table3": {"DP": dp, "HP": hp, "HtoD": htod, "DtoH": dtoh, "DtoD": 0.0,
+                           "P": P_, "T": T_, "TOT": P_ + T_},
+                "paper_tot_seconds": tot, "ratio_paper_over_this": tot / (P_ + T_)}
+            del X, t, Z, Xh, th, pop_h, fit_h
     return {"workload": "shared-gene polytrigo (Eq. 9), 2,100 x 11 binary set replicated to "
                         "0.15/16/128/512 MB of the paper's size, population 23, 4,000 "
-                        "generations, TMSE R = 0.49; data resident in GPU memory",
+                        "generations, TMSE R = 0.49; the patterns start in host memory",
+            "columns": "Table 3: DP device processing (HIP events), HP host processing not "
+                       "covered by device time, HtoD pattern upload, DtoH population and "
+                       "errors back, DtoD none; P = DP + HP, T = HtoD + DtoH + DtoD, "
+                       "TOT = P + T (seconds)",
             "runs": rows,
             "paper_hardware": "GeForce GT540M (Table 3 TOT, host transfers included)"}
+
+
+def form_trig(gg, prob, reps=25):
+    """The trigonometric expansion (Eq. 8) on the scale workload's patterns:
+    degree 4 gives 2 x 20 x 4 + 1 = 161 genes, the same product shape as the
+    Legendre degree-8 headline (M = 200,000, N = 2,048, K = 160), so the two
+    fractions of peak differ only by what the expansion costs: the trig
+    recurrence is seeded with cos x and sin x of each (pattern, feature) in
+    every chromosome tile."""
+    import torch
+    dev = torch.device("cuda:0")
+    P = prob.population
+    X = torch.from_numpy(prob.X).to(dev)
+    t = torch.from_numpy(prob.t).to(dev)
+    cfg = gg.config(basis=gg.GAME_TRIG, degree=4, population=P, seed=0,
+                    max_generations=1 << 30, target=-1.0)
+    game = gg.Game(cfg, X, t)
+    game.init_population()
+    pop, _ = game.population()
+    t_kernel = time_fitness(gg, game, pop, P, reps, torch.cuda.current_stream())
+    game.close()
+    K = gg.game_num_genes(cfg, prob.n_features)
+    flops = 2.0 * (K - 1) * P * prob.n_patterns
+    achieved = flops / t_kernel / 1e12
+    return {"workload": "trig: 200,000 patterns x 20 features, trigonometric degree 4 "
+                        "(161 genes), population 2,048, FP32",
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                         "traffic": profiled_traffic("fitness_f32_trig.md"),
+                         "kernel_ms": t_kernel * 1e3, "kernel_timing": f"median of {reps} launches",
+                         "flops_per_launch": flops}}
 
 
 def form_batched(gg, steps, warmup):
@@ -563,7 +625,7 @@ def main():
                     help="generations of the plain FP32 run that sets the time-to-target goal")
     ap.add_argument("--target-seeds", type=int, default=5,
                     help="GA seeds of the time-to-target comparison (0, 1, ...)")
-    ap.add_argument("--only", choices=["scale", "bf16", "batched", "target", "paper"],
+    ap.add_argument("--only", choices=["scale", "bf16", "batched", "target", "paper", "trig"],
                     help="run one workload alone and print its result (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise kernel of known traffic (256 MiB read, "
@@ -589,8 +651,11 @@ def main():
 
     gg.lib()
     seeds = tuple(range(args.target_seeds))
-    if args.only in ("bf16", "batched", "target", "paper"):
-        if args.only == "bf16":
+    if args.only in ("bf16", "batched", "target", "paper", "trig"):
+        if args.only == "trig":
+            log("trig expansion on the scale patterns: building inputs")
+            res = form_trig(gg, datagen.scale())
+        elif args.only == "bf16":
             log("precision form: building inputs")
             res = form_bf16(gg, precision_problem(), args.steps, args.warmup)
         elif args.only == "batched":
@@ -637,6 +702,8 @@ def main():
         pprob = precision_problem()
         log("precision form: timing")
         forms = {"bf16": form_bf16(gg, pprob, args.steps, args.warmup)}
+        log("trig expansion on the scale patterns")
+        forms["trig"] = form_trig(gg, prob)
         log("batched form: building inputs, autotuning, timing")
         forms["batched"] = form_batched(gg, max(5, args.steps // 5), max(2, args.warmup // 5))
         out["forms"] = forms

@@ -124,7 +124,12 @@ size_t game_workspace_size(const game_config* cfg, int64_t n_patterns, int32_t n
  * X_dev, t_dev and workspace_dev must stay valid and X_dev/t_dev unchanged
  * until game_destroy.  workspace_dev must be 256-byte aligned and at least
  * game_workspace_size() bytes.  Validates the configuration (GAME_EINVAL),
- * the workspace (GAME_EWORKSPACE).  The population is not initialised. */
+ * the workspace (GAME_EWORKSPACE).  The population is not initialised.  For
+ * a float32 run of the trigonometric expansion (Eq. 8), cos x and sin x of
+ * every pattern and feature are computed here once, into the workspace
+ * (n_patterns x n_features x 8 bytes of it), queued on hip_stream: the
+ * trigonometric terms are evaluated once per data set, not in every
+ * generation (Sec. 4.1). */
 int game_create(const game_config* cfg, const float* X_dev, const float* t_dev,
                 int64_t n_patterns, int32_t n_features, void* workspace_dev,
                 size_t workspace_bytes, void* hip_stream, game_t* out);

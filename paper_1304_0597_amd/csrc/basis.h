@@ -61,6 +61,12 @@ struct Recur<3, T> {
     cur = half ? s : c;
     m2 = T(2) * c;
   }
+  // The same seed from a stored (cos x, sin x) pair.
+  __device__ void seed_cs(T c, T s, int half) {
+    prev = half ? T(0) : T(1);
+    cur = half ? s : c;
+    m2 = T(2) * c;
+  }
   template <int J>
   __device__ void advance(T) { T n = fma(m2, cur, -prev); prev = cur; cur = n; }
 };

@@ -94,9 +94,14 @@ struct FitArgs {
   int32_t xcd_remap;
   int32_t error_fn;
   float R;
-  int32_t degree;           // d, read by the run-time-degree body only
+  int32_t degree;           // d
   int32_t basis;            // expansion family, read by the run-time-family body only
+  const float* cs;          // trig only: [NP x N] pairs (cos x, sin x) of X, or null
 };
+
+// Fitness-kernel variant of the trigonometric expansion that reads the
+// stored (cos x, sin x) table FitArgs::cs.
+constexpr int kTrigTable = 4;
 
 // Grid/chunk planning shared by every fitness launch.
 void plan_fitness(FitArgs& a, int degree, int basis);
@@ -111,6 +116,10 @@ constexpr int kMaxTileCols = 128;
 
 // Float64 re-score of n chromosomes over a data set.
 // Per-pattern cos/sin sums of the shared-gene model: Z [NP x 2d].
+// The trigonometric expansion's seeds of a data set, once: cs[2(k N + i)]
+// = cos x_ki, cs[2(k N + i) + 1] = sin x_ki (float32 sincosf, the call the
+// fitness kernels make when no table is given).
+hipError_t launch_trig_cs(const float* X, int64_t NP, int N, float* cs, hipStream_t s);
 hipError_t launch_trig_sums(const float* X, int64_t NP, int N, int d, float* Z, hipStream_t s);
 
 // Outputs (counts == nullptr) or classification counts of n chromosomes.

@@ -26,6 +26,10 @@
 //    running sum.
 //    Partials per (chromosome, split) are combined in a fixed order: the
 //    result does not depend on scheduling.
+//  * The trigonometric expansion (Eq. 8) is seeded with cos x and sin x of
+//    the lane's feature.  For the run's own data set they come from a table
+//    computed once per data set (FitArgs::cs); otherwise sincosf in every
+//    chromosome tile.
 //  * Grid: (pattern split) x (64-chromosome tile); consecutive blocks of one
 //    split are mapped onto one XCD so its L2 serves the split's rows to all
 //    chromosome tiles.
@@ -81,7 +85,7 @@ hipError_t launch_fitness_f32(const FitArgs& a, int basis, int degree, hipStream
     case 0: return launch_basis<0>(a, degree, s);
     case 1: return launch_basis<1>(a, degree, s);
     case 2: return launch_basis<2>(a, degree, s);
-    case 3: return launch_basis<3>(a, degree, s);
+    case 3: return a.cs ? launch_basis<kTrigTable>(a, degree, s) : launch_basis<3>(a, degree, s);
     default: return hipErrorInvalidValue;
   }
 }

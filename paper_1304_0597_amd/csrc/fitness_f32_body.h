@@ -45,7 +45,9 @@ __device__ __forceinline__ gptr_f32 global_f32(const float* p) { return (gptr_f3
 // Tile range [split's tiles] x chromosome tile ctile of the launch described
 // by a_in; writes a.partial[split * ld_partial + chromosome].  genes: the
 // chromosomes being scored; lds: the workgroup's dynamic LDS.  D is the
-// degree.  BASIS is the expansion family, or -1 for the family a_in.basis
+// degree.  BASIS is the expansion family (kTrigTable: the trigonometric one
+// seeded from the stored (cos x, sin x) table a_in.cs instead of sincosf in
+// every tile), or -1 for the family a_in.basis
 // read at run time: the same K-steps in the same order, each recurrence step
 // the table-driven form of Recur<-1> with the bits of the fixed family's, so
 // both forms give the same bits (the batched kernel runs every run's family
@@ -73,9 +75,12 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   a.n_tiles = uniform(a_in.n_tiles);
   a.error_fn = uniform(a_in.error_fn);
   a.R = uniform(a_in.R);
+  constexpr bool kTable = BASIS == kTrigTable;
+  constexpr int FAM = kTable ? 3 : BASIS;   // expansion family (-1: run time)
+  a.cs = kTable ? uniform(a_in.cs) : nullptr;
   static_assert(D >= 1 && D <= kMaxDegree, "compile-time degree");
   constexpr int Dv = D;
-  const int fam = BASIS >= 0 ? BASIS : uniform(a_in.basis);
+  const int fam = FAM >= 0 ? FAM : uniform(a_in.basis);
   const bool trig = fam == 3;
   genes = uniform(genes);
   split = uniform(split);
@@ -143,8 +148,22 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   const int tile_begin = split * a.tiles_per_split;
   const int tile_end = min(tile_begin + a.tiles_per_split, a.n_tiles);
 
-  // x of sub-feature pair q for this lane's two rows (0 outside the data).
-  auto load_x = [&](int64_t row0, int q, float (&xo)[2]) {
+  // x of sub-feature pair q for this lane's two rows (0 outside the data);
+  // from the stored trig table, cos x into xo and sin x into so instead.
+  auto load_x = [&](int64_t row0, int q, float (&xo)[2], float (&so)[2]) {
+    if constexpr (kTable) {
+      typedef float f32x2 __attribute__((ext_vector_type(2)));
+      typedef const f32x2 __attribute__((address_space(1)))* gptr_f32x2;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const int64_t r = row0 + rb * 32 + m;
+        f32x2 v = {0.f, 0.f};
+        if (r < NP) v = ((gptr_f32x2)a.cs)[r * N + q];
+        xo[rb] = v.x;
+        so[rb] = v.y;
+      }
+      return;
+    }
     const int u = 2 * q + h;
     const int f = trig ? q : u;
     const bool fvalid = trig ? true : (u < a.U);
@@ -155,8 +174,8 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
     }
   };
 
-  float xn[2] = {0.f, 0.f};
-  if (tile_begin < tile_end) load_x((int64_t)tile_begin * kTileRows + wave * 64, 0, xn);
+  float xn[2] = {0.f, 0.f}, sn[2] = {0.f, 0.f};
+  if (tile_begin < tile_end) load_x((int64_t)tile_begin * kTileRows + wave * 64, 0, xn, sn);
   // Chunked genes: stage index st runs over (tile, chunk) in loop order and
   // uses buffer st & 1.
   int st = 0;
@@ -196,15 +215,20 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
       const int q_begin = chunk * ppc;
       const int q_end = min(q_begin + ppc, a.Q);
       for (int q = q_begin; q < q_end; ++q) {
-        float x[2] = {xn[0], xn[1]};
+        float x[2] = {xn[0], xn[1]}, sx[2] = {sn[0], sn[1]};
         // prefetch the next pair, or the first pair of the next tile
-        if (q + 1 < a.Q) load_x(row0, q + 1, xn);
-        else if (tile + 1 < tile_end) load_x(row0 + kTileRows, 0, xn);
-        Recur<BASIS> rc[2];
+        if (q + 1 < a.Q) load_x(row0, q + 1, xn, sn);
+        else if (tile + 1 < tile_end) load_x(row0 + kTileRows, 0, xn, sn);
+        Recur<FAM> rc[2];
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
-          if constexpr (BASIS < 0) rc[rb].seed(fam, x[rb], h);
-          else rc[rb].seed(x[rb], h);
+          if constexpr (FAM < 0) {
+            rc[rb].seed(fam, x[rb], h);
+          } else if constexpr (kTable) {
+            rc[rb].seed_cs(x[rb], sx[rb], h);
+          } else {
+            rc[rb].seed(x[rb], h);
+          }
         }
         const float* wl = wbuf + m * WS + (2 * (q - q_begin) + h) * Dv;
         // One K-step per degree: two MFMA columns x two row blocks, then the
@@ -222,7 +246,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
           if constexpr (j + 1 < D) {
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb) {
-              if constexpr (BASIS < 0) rc[rb].template advance_fam<j + 1>(fam);
+              if constexpr (FAM < 0) rc[rb].template advance_fam<j + 1>(fam);
               else rc[rb].template advance<j + 1>(x[rb]);
             }
           }

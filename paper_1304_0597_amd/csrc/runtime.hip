@@ -91,10 +91,16 @@ int check_config(const game_config* c, int32_t n_features) {
 }
 
 struct Layout {
-  size_t state, pop0, pop1, fit32, fit64, order, cum, partial, rescore, total;
+  size_t state, pop0, pop1, fit32, fit64, order, cum, partial, rescore, cs, total;
 };
 
-Layout layout(const game_config* c, int32_t n_features) {
+// The trig expansion's (cos x, sin x) table is kept for float32 runs (the
+// BF16 kernel evaluates them itself).
+bool keeps_trig_table(const game_config* c) {
+  return c->basis == GAME_TRIG && c->precision == GAME_FP32;
+}
+
+Layout layout(const game_config* c, int64_t n_patterns, int32_t n_features) {
   const size_t P = (size_t)c->population;
   const size_t K = (size_t)genes_of(c, n_features);
   const size_t Ppad = (P + kMaxTileCols - 1) / kMaxTileCols * kMaxTileCols;
@@ -110,6 +116,8 @@ Layout layout(const game_config* c, int32_t n_features) {
   L.partial = off;
   off += align_up(std::max(Ppad * kMaxSplits, (size_t)kSplitCapacity) * sizeof(double));
   L.rescore = off; off += align_up(64 * sizeof(double));
+  L.cs = off;
+  if (keeps_trig_table(c)) off += align_up((size_t)n_patterns * n_features * 2 * sizeof(float));
   L.total = off;
   return L;
 }
@@ -135,6 +143,7 @@ struct game_ctx {
   double* cum;              // roulette wheel of the current generation
   double* partial;
   double* rescore;          // float64 error of the last re-scored elite
+  const float* cs;          // (cos x, sin x) of the data set (trig, float32), or null
   bool initialized;
   hipGraphExec_t graph;
   int graph_steps;
@@ -185,6 +194,9 @@ FitArgs fit_args(const game_ctx* h, const float* X, const float* t, int64_t NP, 
   a.partial = h->partial;
   a.error_fn = h->cfg.error_fn;
   a.R = h->cfg.tmse_R;
+  a.degree = h->cfg.degree;
+  a.basis = h->cfg.basis;
+  a.cs = X == h->X && NP == h->NP ? h->cs : nullptr;
   if (h->cfg.precision == GAME_BF16) plan_fitness_bf16(a, h->cfg.degree, h->cfg.basis);
   else plan_fitness(a, h->cfg.degree, h->cfg.basis);
   return a;
@@ -592,7 +604,7 @@ size_t game_workspace_size(const game_config* c, int64_t n_patterns, int32_t n_f
     fail(GAME_EINVAL, "n_patterns < 1");
     return 0;
   }
-  return layout(c, n_features).total;
+  return layout(c, n_patterns, n_features).total;
 }
 
 int game_create(const game_config* c, const float* X, const float* t, int64_t NP, int32_t N,
@@ -607,7 +619,7 @@ int game_create(const game_config* c, const float* X, const float* t, int64_t NP
   if (!X || !t) return fail(GAME_EINVAL, "X or t is NULL");
   if (!ws) return fail(GAME_EWORKSPACE, "workspace is NULL");
   if (!aligned(ws, kAlign)) return fail(GAME_EWORKSPACE, "workspace not 256-byte aligned");
-  const Layout L = layout(c, N);
+  const Layout L = layout(c, NP, N);
   if (ws_bytes < L.total)
     return fail(GAME_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
   game_ctx* h = new game_ctx{};
@@ -628,7 +640,17 @@ int game_create(const game_config* c, const float* X, const float* t, int64_t NP
   h->partial = (double*)(base + L.partial);
   h->cum = (double*)(base + L.cum);
   h->rescore = (double*)(base + L.rescore);
-  hipError_t e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
+  hipError_t e = hipSuccess;
+  if (keeps_trig_table(c)) {
+    float* cs = (float*)(base + L.cs);
+    e = launch_trig_cs(X, NP, N, cs, h->stream);
+    if (e != hipSuccess) {
+      delete h;
+      return hip_fail(e, "launch_trig_cs");
+    }
+    h->cs = cs;
+  }
+  e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete h;
     return hip_fail(e, "hipStreamCreateWithFlags");

@@ -8,6 +8,11 @@
 // One thread per pattern: cos/sin(j x) by the recurrence of Eq. 8 seeded
 // with sincos(x), everything in float64, rounded to float32 once.  The
 // per-degree sums live in registers (degree is a template argument).
+//
+// Also here: the per-feature trigonometric expansion's seeds (cos x, sin x of
+// every pattern and feature), stored once per data set for the float32
+// fitness kernel, which would otherwise evaluate them in every chromosome
+// tile (Sec. 4.1: trigonometric terms computed once, not every iteration).
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -64,7 +69,22 @@ hipError_t dispatch(int d, const float* X, int64_t NP, int N, float* Z, hipStrea
   return e;
 }
 
+__global__ __launch_bounds__(256) void trig_cs_kernel(const float* X, int64_t n, float* cs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float sn, c;
+  sincosf(X[i], &sn, &c);
+  cs[2 * i] = c;
+  cs[2 * i + 1] = sn;
+}
+
 }  // namespace
+
+hipError_t launch_trig_cs(const float* X, int64_t NP, int N, float* cs, hipStream_t s) {
+  const int64_t n = NP * N;
+  hipLaunchKernelGGL(trig_cs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, cs);
+  return hipGetLastError();
+}
 
 hipError_t launch_trig_sums(const float* X, int64_t NP, int N, int d, float* Z, hipStream_t s) {
   return dispatch(d, X, NP, N, Z, s, std::make_integer_sequence<int, kMaxDegree>{});
