@@ -530,10 +530,12 @@ def form_trig(gg, prob, reps=25):
                          "flops_per_launch": flops}}
 
 
-def form_batched(gg, steps, warmup):
+def form_batched(gg, steps, warmup, decomposition=None):
     """Batched form: the 256 runs of the batched workload (sizes drawn from
     seed 3) advanced together, FP32; the autotuner picks the work
-    decomposition, whose fitness launch it times with HIP events."""
+    decomposition, whose fitness launch it times with HIP events
+    (decomposition = (tiles per item, grid) sets it instead, so that a
+    profile traces that decomposition alone)."""
     import torch
     from paper_1304_0597_amd import datagen
     shapes = datagen.batched_shapes()
@@ -549,7 +551,11 @@ def form_batched(gg, steps, warmup):
         flops += 2.0 * sh.n_features * sh.degree * sh.population * sh.n_patterns
     batch = gg.Batch(problems, cfgs)
     batch.init()
-    tune = batch.autotune(reps=3)
+    if decomposition is None:
+        tune = batch.autotune(reps=3)
+    else:
+        batch.tune(*decomposition)
+        tune = {"ms": None, "times_ms": None}
     for _ in range(warmup):
         batch.step()
     torch.cuda.synchronize()
@@ -627,6 +633,8 @@ def main():
                     help="GA seeds of the time-to-target comparison (0, 1, ...)")
     ap.add_argument("--only", choices=["scale", "bf16", "batched", "target", "paper", "trig"],
                     help="run one workload alone and print its result (for profiling)")
+    ap.add_argument("--batch-decomp", type=str, default=None,
+                    help="batched form: 'tiles,grid' instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise kernel of known traffic (256 MiB read, "
                          "256 MiB written per launch) to scale hardware byte counters")
@@ -660,7 +668,8 @@ def main():
             res = form_bf16(gg, precision_problem(), args.steps, args.warmup)
         elif args.only == "batched":
             log("batched form: building inputs, autotuning, timing")
-            res = form_batched(gg, args.steps, args.warmup)
+            dec = tuple(int(v) for v in args.batch_decomp.split(",")) if args.batch_decomp else None
+            res = form_batched(gg, args.steps, args.warmup, dec)
         elif args.only == "target":
             log("time to target: building inputs")
             res = form_time_to_target(gg, precision_problem(), args.target_generations,
