@@ -216,8 +216,29 @@ __global__ __launch_bounds__(64 * bf16_waves(D), 1) void fitness_bf16_kernel(Fit
                                      (__attribute__((address_space(3))) void*)(dst + (N / 4) * 1024),
                                      4, 0, 0);
   };
+  // Every group holds whole sub-features (no ragged last group): then the
+  // features of group g sit at fixed offsets from one per-lane address.
+  // Feature f of row r is at byte (f >> 2) * 1024 + r * 16 + (f & 3) * 4;
+  // with G even, f = 2(gG + i) + h gives g * G * 512 + (i >> 1) * 1024 +
+  // (i & 1) * 8 + h * 4 (trig, G a multiple of 4: f = gG + i gives
+  // g * G * 256 + (i >> 2) * 1024 + (i & 3) * 4).
+  constexpr bool kFixedOffsets = BASIS != 3 || G % 4 == 0;
+  const bool whole_groups =
+      kFixedOffsets && (BASIS == 3 ? G * a.Q == N : 2 * G * a.Q == a.U);
+  const unsigned char* xl_lane = xl_base + m * 16 + (BASIS == 3 ? 0 : h * 4);
   // x of group g from this wave's XL buffer (rows rb*32 + m of the slice).
   auto xl_read = [&](int g, float (&xo)[2][G]) {
+    if (whole_groups) {
+      const unsigned char* src = xl_lane + g * (BASIS == 3 ? G * 256 : G * 512);
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        const int off = BASIS == 3 ? (i >> 2) * 1024 + (i & 3) * 4 : (i >> 1) * 1024 + (i & 1) * 8;
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+          xo[rb][i] = *reinterpret_cast<const float*>(src + off + rb * 512);
+      }
+      return;
+    }
     const unsigned char* src = xl_base;
 #pragma unroll
     for (int i = 0; i < G; ++i) {
@@ -291,27 +312,29 @@ __global__ __launch_bounds__(64 * bf16_waves(D), 1) void fitness_bf16_kernel(Fit
       __asm__ __volatile__("" ::: "memory");
       if (tile + TS < tile_end) xl_issue(tile + TS);
     };
-    // Features of the current group (x) and the next one (xn).
-    float x[2][G], xn[2][G];
+    // Features and recurrences of two consecutive groups: groups alternate
+    // between the A and B sets, so nothing is copied from one group to the
+    // next.
+    float xA[2][G], xB[2][G];
     if constexpr (XL) {
       // This tile's copy (issued after the previous tile's last read) has
       // landed.
       __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
       __asm__ __volatile__("" ::: "memory");
-      xl_read(0, x);
-      xl_read(n_groups > 1 ? 1 : 0, xn);
+      xl_read(0, xA);
+      xl_read(n_groups > 1 ? 1 : 0, xB);
     } else {
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int i = 0; i < G; ++i) x[rb][i] = xt[rb][i];
-      load_x(row0, n_groups > 1 ? 1 : 0, xn);
+        for (int i = 0; i < G; ++i) xA[rb][i] = xt[rb][i];
+      load_x(row0, n_groups > 1 ? 1 : 0, xB);
     }
     // Bias K-step: accumulators start at a_0 - t_k, exactly.  The first
     // K-step's A values are generated meanwhile.
-    Recur<BASIS> rc[2];
+    Recur<BASIS> rcA[2], rcB[2];
     [&]<int... P>(std::integer_sequence<int, P...>) {
-      (gen(std::integral_constant<int, P>{}, rc, x, av[0]), ...);
+      (gen(std::integral_constant<int, P>{}, rcA, xA, av[0]), ...);
     }(std::make_integer_sequence<int, 8>{});
     f32x16 acc[2][4];
 #pragma unroll
@@ -345,13 +368,16 @@ __global__ __launch_bounds__(64 * bf16_waves(D), 1) void fitness_bf16_kernel(Fit
       }
       const int g_begin = chunk * gpc;
       const int g_end = min(g_begin + gpc, n_groups);
-      for (int g = g_begin; g < g_end; ++g) {
+      // Group g with the current set (rc_c, x_c) and the next group's set
+      // (rc_n, x_n); K-step k uses fragment buffer (k + PAR) & 1.
+      auto group = [&](int g, auto par_c, Recur<BASIS> (&rc_c)[2], float (&x_c)[2][G],
+                       Recur<BASIS> (&rc_n)[2], float (&x_n)[2][G]) {
+        constexpr int PAR = decltype(par_c)::value;
         if constexpr (!XL) {
           // The next tile's first features, one group ahead of their use.
           if (g + 1 == n_groups && tile + TS < tile_end) load_x(row0 + TS * kTileRows, 0, xt);
         }
         const int kbase = (g - g_begin) * KS * 32;
-        Recur<BASIS> rcn[2];
         // K-step k: its eight MFMAs, each pair followed by the B fragment of
         // K-step k+1 for that column block and two of K-step k+1's A values
         // (for the last K-step: the next group's first K-step), so the vector
@@ -359,7 +385,7 @@ __global__ __launch_bounds__(64 * bf16_waves(D), 1) void fitness_bf16_kernel(Fit
         // keep that order.
         auto kstep = [&](auto kc) {
           constexpr int k = decltype(kc)::value;
-          constexpr int cur = k & 1, nxt = cur ^ 1;
+          constexpr int cur = (k + PAR) & 1, nxt = cur ^ 1;
           int nb = kbase + (k + 1) * 32;
           nb = nb == chunk_bytes ? 0 : nb;
           auto pair = [&](auto cc) {
@@ -368,11 +394,11 @@ __global__ __launch_bounds__(64 * bf16_waves(D), 1) void fitness_bf16_kernel(Fit
             acc[1][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[cur][1], bq[cur][cb], acc[1][cb], 0, 0, 0);
             bq[nxt][cb] = *reinterpret_cast<const bf16x8*>(wrow + cb * 32 * RS + nb);
             if constexpr (k + 1 < KS) {
-              gen(std::integral_constant<int, 8 * (k + 1) + 2 * cb>{}, rc, x, av[nxt]);
-              gen(std::integral_constant<int, 8 * (k + 1) + 2 * cb + 1>{}, rc, x, av[nxt]);
+              gen(std::integral_constant<int, 8 * (k + 1) + 2 * cb>{}, rc_c, x_c, av[nxt]);
+              gen(std::integral_constant<int, 8 * (k + 1) + 2 * cb + 1>{}, rc_c, x_c, av[nxt]);
             } else {
-              gen(std::integral_constant<int, 2 * cb>{}, rcn, xn, av[nxt]);
-              gen(std::integral_constant<int, 2 * cb + 1>{}, rcn, xn, av[nxt]);
+              gen(std::integral_constant<int, 2 * cb>{}, rc_n, x_n, av[nxt]);
+              gen(std::integral_constant<int, 2 * cb + 1>{}, rc_n, x_n, av[nxt]);
             }
             __builtin_amdgcn_sched_barrier(0);
           };
@@ -384,7 +410,23 @@ __global__ __launch_bounds__(64 * bf16_waves(D), 1) void fitness_bf16_kernel(Fit
         [&]<int... Ks>(std::integer_sequence<int, Ks...>) {
           (kstep(std::integral_constant<int, Ks>{}), ...);
         }(std::make_integer_sequence<int, KS>{});
-        // Advance: the next group's features and recurrence become current.
+        // The current set is done: group g + 2's features go into it.
+        if constexpr (XL) {
+          if (g + 2 < n_groups) xl_read(g + 2, x_c);
+          if (g + 3 == n_groups) xl_release();
+        } else {
+          load_x(row0, g + 2 < n_groups ? g + 2 : n_groups - 1, x_c);
+        }
+      };
+      int g = g_begin;
+      for (; g + 1 < g_end; g += 2) {
+        group(g, std::integral_constant<int, 0>{}, rcA, xA, rcB, xB);
+        group(g + 1, std::integral_constant<int, KS & 1>{}, rcB, xB, rcA, xA);
+      }
+      if (g < g_end) {
+        // A last unpaired group: its successor's set (B) becomes A, group
+        // g + 2's features (now in A) go to B, and fragments to parity 0.
+        group(g, std::integral_constant<int, 0>{}, rcA, xA, rcB, xB);
         if constexpr (KS % 2 == 1) {
 #pragma unroll
           for (int rb = 0; rb < 2; ++rb) av[0][rb] = av[1][rb];
@@ -393,15 +435,13 @@ __global__ __launch_bounds__(64 * bf16_waves(D), 1) void fitness_bf16_kernel(Fit
         }
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
-          rc[rb] = rcn[rb];
+          rcA[rb] = rcB[rb];
 #pragma unroll
-          for (int i = 0; i < G; ++i) x[rb][i] = xn[rb][i];
-        }
-        if constexpr (XL) {
-          if (g + 2 < n_groups) xl_read(g + 2, xn);
-          if (g + 3 == n_groups) xl_release();
-        } else {
-          load_x(row0, g + 2 < n_groups ? g + 2 : n_groups - 1, xn);
+          for (int i = 0; i < G; ++i) {
+            const float t2 = xA[rb][i];
+            xA[rb][i] = xB[rb][i];
+            xB[rb][i] = t2;
+          }
         }
       }
     }
