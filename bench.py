@@ -204,8 +204,8 @@ def form_bf16(gg, prob, steps, warmup):
                                            "float64 re-score on the GPU"}}
 
 
-SURROGATE_CFG = dict(hidden=256, fp32_operands=0, archive=16384, minibatch=1024, train_steps=24,
-                     lr=1.5e-2, oversample=8, audit=64, rho_min=0.8, min_archive=4096, seed=0)
+SURROGATE_CFG = dict(hidden=256, fp32_operands=0, archive=16384, minibatch=1024, train_steps=48,
+                     lr=2e-3, oversample=8, audit=256, rho_min=0.8, min_archive=4096, seed=0)
 
 
 def _run_to_target(gg, prob, precision, cap, val_target=None, train_target=None,

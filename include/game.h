@@ -281,7 +281,11 @@ int game_init_genes(const game_config* cfg, int32_t n_genes, float* out_dev, voi
  * Fitness surrogate: a multilayer perceptron (genes -> standardised log
  * error; two hidden layers of `hidden` units with GELU, one output) trained
  * on the GPU with Adam from an archive of the exact evaluations the GA
- * makes.  Attached to a run it pre-screens offspring: each generation
+ * makes.  The network's inputs are the genes standardised per gene,
+ * x = (g - mean) * inv_std in float32 (two roundings), with the mean and
+ * the inverse standard deviation (population form, deviation floored at
+ * 1e-3) of the archived chromosomes, recomputed after every archived
+ * generation; a new surrogate starts with mean 0 and inv_std 1.  Attached to a run it pre-screens offspring: each generation
  * builds oversample x (P - E) children with the same draws as the plain
  * genetic step (the first P - E of them are exactly the plain offspring),
  * scores them with the network, and keeps the P - E best-predicted ones.
@@ -298,10 +302,10 @@ typedef struct {
   int32_t fp32_operands;  /* 0: BF16 operands, FP32 accumulation; 1: FP32      */
   int32_t archive;        /* archive capacity in chromosomes (16384)          */
   int32_t minibatch;      /* rows per Adam step (1024)                        */
-  int32_t train_steps;    /* Adam steps per generation (24)                   */
-  float lr;               /* Adam learning rate (1.5e-2)                      */
+  int32_t train_steps;    /* Adam steps per generation (48)                   */
+  float lr;               /* Adam learning rate (2e-3)                        */
   int32_t oversample;     /* children generated per kept child (8)            */
-  int32_t audit;          /* children scored exactly per generation (64)      */
+  int32_t audit;          /* children scored exactly per generation (256)     */
   float rho_min;          /* rank correlation needed to screen (0.8)          */
   int32_t min_archive;    /* archive size needed to screen (4096)             */
   uint64_t seed;          /* initial weights and sampling draws (stream 3)    */
@@ -322,13 +326,18 @@ int game_surrogate_create(const game_surrogate_config* cfg, int32_t n_genes, int
                           game_surrogate_t* out);
 int game_surrogate_destroy(game_surrogate_t s);
 
+/* The input statistics in use: mean_dev [n_genes] and inv_std_dev
+ * [n_genes] float32 (on the stream). */
+int game_surrogate_get_input_stats(game_surrogate_t s, float* mean_dev, float* inv_std_dev);
+
 /* Number of parameters; they are one float32 vector in the order W1
  * [hidden x n_genes], b1, W2 [hidden x hidden], b2, w3 [hidden], b3. */
 int64_t game_surrogate_num_params(game_surrogate_t s);
 int game_surrogate_get_params(game_surrogate_t s, float* params_dev);
 int game_surrogate_set_params(game_surrogate_t s, const float* params_dev);
 
-/* Predictions y_dev [n] for genes_dev [n x n_genes], 1 <= n <= max_batch.
+/* Predictions y_dev [n] for genes_dev [n x n_genes] (standardised with the
+ * current input statistics), 1 <= n <= max_batch.
  * A row's prediction does not depend on n or on the other rows: every
  * product sums in one fixed order whatever the batch size. */
 int game_surrogate_predict(game_surrogate_t s, const float* genes_dev, int32_t n, float* y_dev);

@@ -1,6 +1,7 @@
 """Fitness-surrogate network in float64: a multilayer perceptron with GELU
 hidden layers, its loss, analytic gradients, Adam update, parameter
-initialisation and the Spearman rank correlation used to assess it.
+initialisation, the per-gene standardisation of its inputs and the
+Spearman rank correlation used to assess it.
 
 Test infrastructure (see ``oracle/__init__.py``).  The network maps a
 chromosome's genes to a standardised log error:
@@ -113,6 +114,28 @@ def adam_step(params, grads, m, v, step: int, lr=1e-3, beta1=0.9, beta2=0.999, e
         out_m.append(mm)
         out_v.append(vv)
     return out_p, out_m, out_v
+
+
+INPUT_STD_FLOOR = 1e-3
+
+
+def input_stats(genes, floor=INPUT_STD_FLOOR):
+    """Per-gene mean and inverse standard deviation of archived chromosomes
+    [rows x K]: float64 moments, population form (divide by the row count),
+    the deviation floored at `floor`, each rounded once to float32."""
+    G = np.asarray(genes, dtype=np.float64)
+    mean = G.mean(axis=0)
+    var = np.maximum((G * G).mean(axis=0) - mean * mean, 0.0)
+    inv = 1.0 / np.maximum(np.sqrt(var), floor)
+    return mean.astype(np.float32), inv.astype(np.float32)
+
+
+def standardize(genes, mean, inv_std):
+    """The network's inputs: (g - mean) * inv_std per gene, each step one
+    float32 rounding."""
+    G = np.asarray(genes, dtype=np.float32)
+    return ((G - np.asarray(mean, np.float32)).astype(np.float32) *
+            np.asarray(inv_std, np.float32)).astype(np.float32)
 
 
 def ranks(a):

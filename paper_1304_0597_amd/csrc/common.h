@@ -322,6 +322,7 @@ hipError_t launch_out_layer(const float* H2, const float* w3, const float* b3, i
                             float* y, const float* t, const float* Z2, float* dy, float* dZ2,
                             int32_t* step, const int32_t* skip, hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+hipError_t launch_fill(float* p, int64_t n, float value, hipStream_t s);
 
 struct SurrogateState {
   int32_t step;             // Adam steps taken
@@ -382,17 +383,37 @@ struct ArchiveArgs {
 hipError_t launch_archive_append(const ArchiveArgs& a, hipStream_t s);
 hipError_t launch_archive_stats(const float* target, SurrogateState* st, const RunState* run,
                                 int P, int capacity, hipStream_t s);
+// Network inputs are standardised genes, (g - mu) * inv per gene (two
+// float32 roundings); mu and inv come from the archive (launch_gene_stats).
 hipError_t launch_sample_minibatch(const float* genes, const float* target, int32_t K,
                                    const SurrogateState* st, const RunState* run, uint64_t seed,
-                                   int32_t step, int32_t B, float* Xb, float* tb, hipStream_t s);
+                                   int32_t step, int32_t B, const float* mu, const float* inv,
+                                   float* Xb, float* tb, hipStream_t s);
 // The Adam update of a training step and the minibatch draw of the next one
 // (independent work) in one launch.
 hipError_t launch_adam_sample(float* p, const float* part, int ks, float* m, float* v, int64_t n,
                               float lr, SurrogateState* st, const int32_t* skip, const float* genes,
                               const float* target, int32_t K, const RunState* run, uint64_t seed,
-                              int32_t next_step, int32_t B, float* Xb, float* tb, hipStream_t s);
+                              int32_t next_step, int32_t B, const float* mu, const float* inv,
+                              float* Xb, float* tb, hipStream_t s);
+// Audit sample: raw genes (for the exact evaluation) and their standardised
+// copy (for the network).
 hipError_t launch_audit_pick(const float* cand, int32_t C, int32_t K, const RunState* run,
-                             uint64_t seed, int32_t A, float* genes, hipStream_t s);
+                             uint64_t seed, int32_t A, const float* mu, const float* inv,
+                             float* genes, float* x, hipStream_t s);
+// Per-gene mean and inverse standard deviation of the archive's rows
+// (float64 moments summed in a fixed order, population form, the standard
+// deviation floored at kInputStdFloor): part holds 2 * kMomentBlocks * K
+// doubles.
+constexpr int kMomentBlocks = 64;
+constexpr double kInputStdFloor = 1e-3;
+hipError_t launch_gene_stats(const float* genes, int32_t K, int32_t capacity,
+                             const SurrogateState* st, const RunState* run, double* part,
+                             float* mu, float* inv, hipStream_t s);
+// dst[r * K + g] = (src[r * K + g] - mu[g]) * inv[g] for n rows (nothing
+// when *skip is set).
+hipError_t launch_standardize(const float* src, int32_t n, int32_t K, const float* mu,
+                              const float* inv, float* dst, const int32_t* skip, hipStream_t s);
 hipError_t launch_spearman_gate(const float* pred, const float* exact, int32_t A, float rho_min,
                                 int32_t min_archive, const RunState* run, SurrogateState* st,
                                 hipStream_t s);

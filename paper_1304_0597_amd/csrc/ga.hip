@@ -689,28 +689,110 @@ hipError_t launch_archive_stats(const float* target, SurrogateState* st, const R
   return hipGetLastError();
 }
 
+// Input statistics: every gene centred on its archive mean and scaled by
+// its archive spread, so that the network resolves the small differences
+// between a converging population's chromosomes.  Workgroup b sums rows
+// [b * per, (b + 1) * per) of the archive per gene in float64 (one thread
+// per gene, rows in order: coalesced reads of each row); then one thread
+// per gene adds the kMomentBlocks shares in workgroup order.
+__global__ __launch_bounds__(256) void gene_moments_kernel(const float* genes, int K, int capacity,
+                                                          const SurrogateState* st,
+                                                          const RunState* run, double* part) {
+  if (run->stop) return;
+  const int count = st->count;
+  const int per = (capacity + kMomentBlocks - 1) / kMomentBlocks;
+  const int r0 = blockIdx.x * per;
+  const int r1 = min(r0 + per, count);
+  for (int g = threadIdx.x; g < K; g += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int r = r0; r < r1; ++r) {
+      const double v = genes[(int64_t)r * K + g];
+      a += v;
+      b += v * v;
+    }
+    part[(int64_t)blockIdx.x * K + g] = a;
+    part[(int64_t)(kMomentBlocks + blockIdx.x) * K + g] = b;
+  }
+}
+
+__global__ void gene_stats_kernel(const double* part, int K, const SurrogateState* st,
+                                  const RunState* run, float* mu, float* inv) {
+  if (run->stop) return;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int count = st->count;
+  if (g >= K || count < 1) return;
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < kMomentBlocks; ++k) {
+    a += part[(int64_t)k * K + g];
+    b += part[(int64_t)(kMomentBlocks + k) * K + g];
+  }
+  const double m = a / count;
+  const double var = fmax(b / count - m * m, 0.0);
+  mu[g] = (float)m;
+  inv[g] = (float)(1.0 / fmax(sqrt(var), kInputStdFloor));
+}
+
+hipError_t launch_gene_stats(const float* genes, int32_t K, int32_t capacity,
+                             const SurrogateState* st, const RunState* run, double* part,
+                             float* mu, float* inv, hipStream_t s) {
+  hipLaunchKernelGGL(gene_moments_kernel, dim3(kMomentBlocks), dim3(256), 0, s, genes, K, capacity,
+                     st, run, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gene_stats_kernel, dim3((K + 255) / 256), dim3(256), 0, s, part, K, st, run,
+                     mu, inv);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ float standardize1(float g, float mu, float inv) {
+  return __fmul_rn(__fsub_rn(g, mu), inv);
+}
+
+__global__ void standardize_kernel(const float* src, int64_t n, int K, const float* mu,
+                                   const float* inv, float* dst, const int32_t* skip) {
+  if (skip && *skip) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int g = (int)(i % K);
+    dst[i] = standardize1(src[i], mu[g], inv[g]);
+  }
+}
+
+hipError_t launch_standardize(const float* src, int32_t n, int32_t K, const float* mu,
+                              const float* inv, float* dst, const int32_t* skip, hipStream_t s) {
+  const int64_t total = (int64_t)n * K;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(standardize_kernel, dim3(blocks), dim3(256), 0, s, src, total, K, mu, inv,
+                     dst, skip);
+  return hipGetLastError();
+}
+
 // Minibatch of B archive rows drawn with replacement: row b is
 // (u32 * count) >> 32 with u32 = lo32(o0) of key (seed, 3), counter
-// (generation, 1 + step, b, 0); targets standardised.
+// (generation, 1 + step, b, 0); genes and targets standardised.
 __device__ __forceinline__ void sample_minibatch_body(int64_t i, const float* genes,
                                                       const float* target, int K,
                                                       const SurrogateState* st,
                                                       const RunState* run, uint64_t seed, int step,
-                                                      int B, float* Xb, float* tb) {
+                                                      int B, const float* mu, const float* inv,
+                                                      float* Xb, float* tb) {
   if (i >= (int64_t)B * K) return;
   const int b = (int)(i / K), g = (int)(i - (int64_t)b * K);
   const U64x4 r = draw(seed, 3, (uint64_t)run->evaluated, (uint64_t)(1 + step), (uint64_t)b);
   const int idx = (int)(((r.o0 & 0xFFFFFFFFull) * (uint64_t)st->count) >> 32);
-  Xb[i] = genes[(int64_t)idx * K + g];
+  Xb[i] = standardize1(genes[(int64_t)idx * K + g], mu[g], inv[g]);
   if (g == 0) tb[b] = (target[idx] - st->mean) * st->inv_std;
 }
 
 __global__ void sample_minibatch_kernel(const float* genes, const float* target, int K,
                                         const SurrogateState* st, const RunState* run,
-                                        uint64_t seed, int step, int B, float* Xb, float* tb) {
+                                        uint64_t seed, int step, int B, const float* mu,
+                                        const float* inv, float* Xb, float* tb) {
   if (run->stop) return;
   sample_minibatch_body((int64_t)blockIdx.x * blockDim.x + threadIdx.x, genes, target, K, st, run,
-                        seed, step, B, Xb, tb);
+                        seed, step, B, mu, inv, Xb, tb);
 }
 
 // Workgroups [0, adam_blocks) update the parameters; the rest draw the next
@@ -719,7 +801,7 @@ __global__ void adam_sample_kernel(float* p, const float* part, int ks, float* m
                                    int64_t n, float lr, SurrogateState* st, const int32_t* skip,
                                    int adam_blocks, const float* genes, const float* target, int K,
                                    const RunState* run, uint64_t seed, int next_step, int B,
-                                   float* Xb, float* tb) {
+                                   const float* mu, const float* inv, float* Xb, float* tb) {
   if (skip && *skip) return;
   if ((int)blockIdx.x < adam_blocks) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -727,27 +809,29 @@ __global__ void adam_sample_kernel(float* p, const float* part, int ks, float* m
     return;
   }
   sample_minibatch_body((int64_t)(blockIdx.x - adam_blocks) * blockDim.x + threadIdx.x, genes,
-                        target, K, st, run, seed, next_step, B, Xb, tb);
+                        target, K, st, run, seed, next_step, B, mu, inv, Xb, tb);
 }
 
 hipError_t launch_adam_sample(float* p, const float* part, int ks, float* m, float* v, int64_t n,
                               float lr, SurrogateState* st, const int32_t* skip, const float* genes,
                               const float* target, int32_t K, const RunState* run, uint64_t seed,
-                              int32_t next_step, int32_t B, float* Xb, float* tb, hipStream_t s) {
+                              int32_t next_step, int32_t B, const float* mu, const float* inv,
+                              float* Xb, float* tb, hipStream_t s) {
   const int adam_blocks = (int)((n + 255) / 256);
   const int sample_blocks = (int)(((int64_t)B * K + 255) / 256);
   hipLaunchKernelGGL(adam_sample_kernel, dim3((unsigned)(adam_blocks + sample_blocks)), dim3(256),
                      0, s, p, part, ks, m, v, n, lr, st, skip, adam_blocks, genes, target, K, run,
-                     seed, next_step, B, Xb, tb);
+                     seed, next_step, B, mu, inv, Xb, tb);
   return hipGetLastError();
 }
 
 hipError_t launch_sample_minibatch(const float* genes, const float* target, int32_t K,
                                    const SurrogateState* st, const RunState* run, uint64_t seed,
-                                   int32_t step, int32_t B, float* Xb, float* tb, hipStream_t s) {
+                                   int32_t step, int32_t B, const float* mu, const float* inv,
+                                   float* Xb, float* tb, hipStream_t s) {
   const int64_t n = (int64_t)B * K;
   hipLaunchKernelGGL(sample_minibatch_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                     genes, target, K, st, run, seed, step, B, Xb, tb);
+                     genes, target, K, st, run, seed, step, B, mu, inv, Xb, tb);
   return hipGetLastError();
 }
 
@@ -755,21 +839,25 @@ hipError_t launch_sample_minibatch(const float* genes, const float* target, int3
 // (seed, 3), counter (generation, 0x7FFFFFFF, a, 0)); their genes are copied
 // out to be scored by the network and exactly.
 __global__ void audit_pick_kernel(const float* cand, int C, int K, const RunState* run,
-                                  uint64_t seed, int A, float* genes) {
+                                  uint64_t seed, int A, const float* mu, const float* inv,
+                                  float* genes, float* x) {
   if (run->stop) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)A * K) return;
   const int a = (int)(i / K), g = (int)(i - (int64_t)a * K);
   const U64x4 r = draw(seed, 3, (uint64_t)run->gen, 0x7FFFFFFFull, (uint64_t)a);
   const int idx = (int)(((r.o0 & 0xFFFFFFFFull) * (uint64_t)C) >> 32);
-  genes[i] = cand[(int64_t)idx * K + g];
+  const float v = cand[(int64_t)idx * K + g];
+  genes[i] = v;
+  x[i] = standardize1(v, mu[g], inv[g]);
 }
 
 hipError_t launch_audit_pick(const float* cand, int32_t C, int32_t K, const RunState* run,
-                             uint64_t seed, int32_t A, float* genes, hipStream_t s) {
+                             uint64_t seed, int32_t A, const float* mu, const float* inv,
+                             float* genes, float* x, hipStream_t s) {
   const int64_t n = (int64_t)A * K;
   hipLaunchKernelGGL(audit_pick_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cand,
-                     C, K, run, seed, A, genes);
+                     C, K, run, seed, A, mu, inv, genes, x);
   return hipGetLastError();
 }
 

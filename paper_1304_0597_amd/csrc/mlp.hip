@@ -548,18 +548,20 @@ hipError_t launch_sum_ranges(float* g, const float* part, int ks, int64_t n, hip
 
 // Fills n floats with zero (used instead of a memset so the work can sit in
 // a captured graph).
-__global__ void fill_zero_kernel(float* p, int64_t n) {
+__global__ void fill_kernel(float* p, int64_t n, float value) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0.f;
+    p[i] = value;
 }
 
-hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s) {
+hipError_t launch_fill(float* p, int64_t n, float value, hipStream_t s) {
   int blocks = (int)((n + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks), dim3(256), 0, s, p, n);
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, s, p, n, value);
   return hipGetLastError();
 }
+
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s) { return launch_fill(p, n, 0.f, s); }
 
 }  // namespace game

@@ -170,6 +170,10 @@ struct game_surrogate_ctx {
   float *H1c, *H2c, *yc;
   // archive of exact evaluations
   float *arch_genes, *arch_target;
+  // input statistics (per gene: mean, inverse standard deviation) and the
+  // standardised copies of the candidates and of the audit sample
+  float *mu, *inv, *cand_x, *audit_x;
+  double* gpart;
   // screening
   float* cand;
   int32_t* rank;
@@ -250,7 +254,7 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // ----------------------------------------------------------- surrogate
 struct SurLayout {
   size_t st, params, grads, m, v, Xb, tb, Z1, H1, Z2, H2, y, dy, dZ2, dZ1, H1c, H2c, yc, ag, at,
-      cand, rank, sorted, aug, aup, aue, H1a, H2a, kpart, total;
+      cand, rank, sorted, aug, aup, aue, H1a, H2a, kpart, mu, inv, candx, audx, gpart, total;
   int64_t n_params;
 };
 
@@ -290,6 +294,11 @@ SurLayout sur_layout(const game_surrogate_config* c, int32_t n_in, int32_t max_b
   L.H1a = take(A * H * 4);
   L.H2a = take(A * H * 4);
   L.kpart = take((size_t)gemm_k_split((int)B) * P);
+  L.mu = take((size_t)n_in * 4);
+  L.inv = take((size_t)n_in * 4);
+  L.candx = take(C * n_in * 4);
+  L.audx = take(A * n_in * 4);
+  L.gpart = take((size_t)2 * kMomentBlocks * n_in * 8);
   L.total = off;
   return L;
 }
@@ -417,10 +426,12 @@ int enqueue_screening(game_ctx* h, hipStream_t s) {
   aa.st = sr->st;
   GAME_HIP(launch_archive_append(aa, s));
   GAME_HIP(launch_archive_stats(sr->arch_target, sr->st, h->state, P, c.archive, s));
+  GAME_HIP(launch_gene_stats(sr->arch_genes, K, c.archive, sr->st, h->state, sr->gpart, sr->mu,
+                             sr->inv, s));
   // Each Adam update shares its launch with the next step's minibatch draw.
   if (c.train_steps > 0)
     GAME_HIP(launch_sample_minibatch(sr->arch_genes, sr->arch_target, K, sr->st, h->state, c.seed,
-                                     0, c.minibatch, sr->Xb, sr->tb, s));
+                                     0, c.minibatch, sr->mu, sr->inv, sr->Xb, sr->tb, s));
   for (int step = 0; step < c.train_steps; ++step) {
     int ks = 1;
     int rc = sur_gradients(sr, c.minibatch, stop, s, true, &ks);
@@ -428,7 +439,8 @@ int enqueue_screening(game_ctx* h, hipStream_t s) {
     if (step + 1 < c.train_steps)
       GAME_HIP(launch_adam_sample(sr->params, sr->kpart, ks, sr->m, sr->v, sr->n_params, c.lr,
                                   sr->st, stop, sr->arch_genes, sr->arch_target, K, h->state,
-                                  c.seed, step + 1, c.minibatch, sr->Xb, sr->tb, s));
+                                  c.seed, step + 1, c.minibatch, sr->mu, sr->inv, sr->Xb, sr->tb,
+                                  s));
     else
       GAME_HIP(launch_adam(sr->params, sr->kpart, ks, sr->m, sr->v, sr->n_params, c.lr, sr->st,
                            stop, s));
@@ -450,8 +462,9 @@ int enqueue_screening(game_ctx* h, hipStream_t s) {
   // The audit decides first: the network and the exact fitness score a
   // random sample of the candidates, and only when their rank correlation
   // passes does the network score and rank every candidate.
-  GAME_HIP(launch_audit_pick(sr->cand, C, K, h->state, c.seed, c.audit, sr->audit_genes, s));
-  int rc = sur_forward(sr, sr->audit_genes, c.audit, nullptr, sr->H1a, nullptr, sr->H2a,
+  GAME_HIP(launch_audit_pick(sr->cand, C, K, h->state, c.seed, c.audit, sr->mu, sr->inv,
+                             sr->audit_genes, sr->audit_x, s));
+  int rc = sur_forward(sr, sr->audit_x, c.audit, nullptr, sr->H1a, nullptr, sr->H2a,
                        sr->audit_pred, stop, s);
   if (rc) return rc;
   FitArgs fa = fit_args(h, h->X, h->t, h->NP, sr->audit_genes, c.audit);
@@ -462,7 +475,8 @@ int enqueue_screening(game_ctx* h, hipStream_t s) {
   GAME_HIP(launch_spearman_gate(sr->audit_pred, sr->audit_exact, c.audit, c.rho_min,
                                 c.min_archive, h->state, sr->st, s));
   const int32_t* skip = &sr->st->skip;
-  rc = sur_forward(sr, sr->cand, C, nullptr, sr->H1c, nullptr, sr->H2c, sr->yc, skip, s);
+  GAME_HIP(launch_standardize(sr->cand, C, K, sr->mu, sr->inv, sr->cand_x, skip, s));
+  rc = sur_forward(sr, sr->cand_x, C, nullptr, sr->H1c, nullptr, sr->H2c, sr->yc, skip, s);
   if (rc) return rc;
   GAME_HIP(launch_rank_sorted(sr->yc, C, sr->sorted, sr->rank, skip, s));
   GAME_HIP(launch_gather_next(sr->cand, sr->rank, C, K, E, P, h->state, sr->st, h->pop[0],
@@ -1081,15 +1095,17 @@ int game_surrogate_config_default(game_surrogate_config* c) {
   c->hidden = 256;
   c->fp32_operands = 0;
   // Tuned on the 1M x 32, degree-8 problem with population 4,096 for the
-  // time to reach a target error: a window of the last four generations and
-  // 24 Adam steps at 1.5e-2 per generation (rank correlations 0.8-0.9 after
-  // ~40 generations; more steps screen more generations but cost more).
+  // time to reach a target error, with the inputs standardised per gene: a
+  // window of the last four generations, 48 Adam steps at 2e-3 per
+  // generation (the audit's rank correlation above 0.8 from the fifth
+  // generation on), 256 audited children (standard error of the
+  // correlation about 0.02).
   c->archive = 16384;
   c->minibatch = 1024;
-  c->train_steps = 24;
-  c->lr = 1.5e-2f;
+  c->train_steps = 48;
+  c->lr = 2e-3f;
   c->oversample = 8;
-  c->audit = 64;
+  c->audit = 256;
   c->rho_min = 0.8f;
   c->min_archive = 4096;
   c->seed = 0;
@@ -1150,7 +1166,15 @@ int game_surrogate_create(const game_surrogate_config* c, int32_t n_genes, int32
   s->H1a = (float*)(b + L.H1a);
   s->H2a = (float*)(b + L.H2a);
   s->kpart = (float*)(b + L.kpart);
+  s->mu = (float*)(b + L.mu);
+  s->inv = (float*)(b + L.inv);
+  s->cand_x = (float*)(b + L.candx);
+  s->audit_x = (float*)(b + L.audx);
+  s->gpart = (double*)(b + L.gpart);
   hipError_t e = launch_fill_zero((float*)s->st, sizeof(SurrogateState) / sizeof(float), s->stream);
+  // input statistics start as the identity (mean 0, inverse deviation 1)
+  if (e == hipSuccess) e = launch_fill_zero(s->mu, n_genes, s->stream);
+  if (e == hipSuccess) e = launch_fill(s->inv, n_genes, 1.f, s->stream);
   if (e == hipSuccess) e = launch_fill_zero(s->m, s->n_params, s->stream);
   if (e == hipSuccess) e = launch_fill_zero(s->v, s->n_params, s->stream);
   if (e == hipSuccess) e = launch_mlp_init(s->params, n_genes, s->H, c->seed, s->stream);
@@ -1173,6 +1197,15 @@ int64_t game_surrogate_num_params(game_surrogate_t s) {
   return s->n_params;
 }
 
+int game_surrogate_get_input_stats(game_surrogate_t s, float* mean, float* inv_std) {
+  if (!s || !mean || !inv_std) return fail(GAME_EINVAL, "NULL argument");
+  GAME_HIP(hipMemcpyAsync(mean, s->mu, sizeof(float) * s->n_in, hipMemcpyDeviceToDevice,
+                          s->stream));
+  GAME_HIP(hipMemcpyAsync(inv_std, s->inv, sizeof(float) * s->n_in, hipMemcpyDeviceToDevice,
+                          s->stream));
+  return GAME_OK;
+}
+
 int game_surrogate_get_params(game_surrogate_t s, float* params) {
   if (!s || !params) return fail(GAME_EINVAL, "NULL argument");
   GAME_HIP(hipMemcpyAsync(params, s->params, sizeof(float) * s->n_params, hipMemcpyDeviceToDevice,
@@ -1190,7 +1223,8 @@ int game_surrogate_set_params(game_surrogate_t s, const float* params) {
 int game_surrogate_predict(game_surrogate_t s, const float* genes, int32_t n, float* y) {
   if (!s || !genes || !y) return fail(GAME_EINVAL, "NULL argument");
   if (n < 1 || n > s->max_batch) return fail(GAME_EINVAL, "n %d not in 1..%d", n, s->max_batch);
-  int rc = sur_forward(s, genes, n, nullptr, s->H1c, nullptr, s->H2c, y, nullptr, s->stream);
+  GAME_HIP(launch_standardize(genes, n, s->n_in, s->mu, s->inv, s->cand_x, nullptr, s->stream));
+  int rc = sur_forward(s, s->cand_x, n, nullptr, s->H1c, nullptr, s->H2c, y, nullptr, s->stream);
   return rc;
 }
 
@@ -1199,8 +1233,7 @@ int game_surrogate_gradients(game_surrogate_t s, const float* genes, const float
   if (!s || !genes || !target || !grads) return fail(GAME_EINVAL, "NULL argument");
   if (n < 1 || n > s->cfg.minibatch)
     return fail(GAME_EINVAL, "n %d not in 1..minibatch (%d)", n, s->cfg.minibatch);
-  GAME_HIP(hipMemcpyAsync(s->Xb, genes, sizeof(float) * n * s->n_in, hipMemcpyDeviceToDevice,
-                          s->stream));
+  GAME_HIP(launch_standardize(genes, n, s->n_in, s->mu, s->inv, s->Xb, nullptr, s->stream));
   GAME_HIP(hipMemcpyAsync(s->tb, target, sizeof(float) * n, hipMemcpyDeviceToDevice, s->stream));
   int ks = 1;
   int rc = sur_gradients(s, n, nullptr, s->stream, false, &ks);
@@ -1217,8 +1250,7 @@ int game_surrogate_train_step(game_surrogate_t s, const float* genes, const floa
   if (!s || !genes || !target) return fail(GAME_EINVAL, "NULL argument");
   if (n < 1 || n > s->cfg.minibatch)
     return fail(GAME_EINVAL, "n %d not in 1..minibatch (%d)", n, s->cfg.minibatch);
-  GAME_HIP(hipMemcpyAsync(s->Xb, genes, sizeof(float) * n * s->n_in, hipMemcpyDeviceToDevice,
-                          s->stream));
+  GAME_HIP(launch_standardize(genes, n, s->n_in, s->mu, s->inv, s->Xb, nullptr, s->stream));
   GAME_HIP(hipMemcpyAsync(s->tb, target, sizeof(float) * n, hipMemcpyDeviceToDevice, s->stream));
   int ks = 1;
   int rc = sur_gradients(s, n, nullptr, s->stream, true, &ks);

@@ -94,6 +94,7 @@ _SIGS = {
     "game_surrogate_destroy": (c_int32, [c_void_p]),
     "game_surrogate_num_params": (c_int64, [c_void_p]),
     "game_surrogate_get_params": (c_int32, [c_void_p, c_void_p]),
+    "game_surrogate_get_input_stats": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "game_surrogate_set_params": (c_int32, [c_void_p, c_void_p]),
     "game_surrogate_predict": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p]),
     "game_surrogate_gradients": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
@@ -706,6 +707,15 @@ def game_surrogate_get_params(s, params) -> None:
     _check(lib().game_surrogate_get_params(s, _ptr(params, torch.float32)))
 
 
+def game_surrogate_get_input_stats(s, mean, inv_std) -> None:
+    import torch
+    n = _dims(s)["n_genes"]
+    _numel(mean, n, "mean")
+    _numel(inv_std, n, "inv_std")
+    _check(lib().game_surrogate_get_input_stats(s, _ptr(mean, torch.float32),
+                                                _ptr(inv_std, torch.float32)))
+
+
 def game_surrogate_set_params(s, params) -> None:
     import torch
     _numel(params, _dims(s)["n_params"], "params")
@@ -784,6 +794,15 @@ class Surrogate:
 
     def set_params(self, p):
         game_surrogate_set_params(self.h, p)
+
+    def input_stats(self):
+        """(mean, inv_std) of the network's input standardisation."""
+        import torch
+        n = self.n_genes
+        mu = torch.empty(n, dtype=torch.float32, device=self.workspace.device)
+        inv = torch.empty(n, dtype=torch.float32, device=self.workspace.device)
+        game_surrogate_get_input_stats(self.h, mu, inv)
+        return mu, inv
 
     def predict(self, genes):
         import torch

@@ -194,6 +194,42 @@ def test_fallback_reproduces_the_plain_run(gg):
     s.close()
 
 
+@pytest.mark.parametrize("fp32", [True, False])
+def test_input_stats_follow_the_archive(gg, fp32):
+    """The network's inputs are the genes standardised with the archive's
+    per-gene mean and inverse deviation.  After five screened generations
+    (the archive holds all of them) the device statistics equal the oracle's
+    over those five populations, and a prediction equals the float64
+    network on the oracle-standardised genes."""
+    prob = _problem(n=3000)
+    P = prob.population
+    g = _game(gg, prob)
+    s = make(gg, prob.n_genes, fp32, H=64, minibatch=128, max_batch=8 * (P - 2), rho_min=-1.0,
+             min_archive=0, audit=16, archive=4096, train_steps=4)
+    mu0, inv0 = s.input_stats()
+    assert np.all(mu0.cpu().numpy() == 0) and np.all(inv0.cpu().numpy() == 1)
+    gg.game_attach_surrogate(g.h, s.h)
+    g.init_population()
+    pops = []
+    for _ in range(5):
+        pops.append(g.population()[0].cpu().numpy().copy())
+        g.step()
+    mu, inv = (x.cpu().numpy() for x in s.input_stats())
+    ref_mu, ref_inv = mlp.input_stats(np.concatenate(pops))
+    np.testing.assert_allclose(mu, ref_mu, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(inv, ref_inv, rtol=1e-6)
+    genes = g.population()[0]
+    y = s.predict(genes).cpu().numpy()
+    params = [np.asarray(x, np.float64) for x in split(s.params().cpu().numpy(), prob.n_genes, 64)]
+    ref_y, _ = mlp.forward(params, mlp.standardize(genes.cpu().numpy(), mu, inv))
+    if fp32:
+        assert rel_l2(y, ref_y) < 1e-4
+    else:
+        assert cosine(y, ref_y) > 0.999 and rel_l2(y, ref_y) < 2e-2
+    g.close()
+    s.close()
+
+
 def _best_after(gg, prob, generations, sur=None, seed=1):
     g = _game(gg, prob, seed=seed)
     if sur is not None:
@@ -208,27 +244,31 @@ def _best_after(gg, prob, generations, sur=None, seed=1):
 
 
 def test_trained_surrogate_gains_over_plain(gg):
-    """Paired runs, same seed and problem.  With the surrogate the run makes
-    P + audit exact evaluations per generation, so the plain run gets the
-    same exact-evaluation budget (more generations).  The screened run must
-    reach a lower best error than the plain one in the median over seeds."""
+    """Paired runs, same seed and problem, the default gate (rank correlation
+    0.8 on the audit).  With the surrogate the run makes P + audit exact
+    evaluations per generation, so the plain run gets the same
+    exact-evaluation budget (more generations).  Stated margin: in the
+    median over three seeds the screened run's best error is at least 1.25x
+    lower than the plain run's, with the network trusted in at least half
+    of the generations."""
     prob = _problem()
     P = prob.population
     G = 40
-    audit = 16
+    audit = 32
     budget_G = int(np.ceil(G * (P + audit) / P))
-    gains = []
+    gains, trusted = [], []
     for seed in (1, 2, 3):
         plain = _best_after(gg, prob, budget_G, seed=seed)
         s = make(gg, prob.n_genes, False, H=64, minibatch=512, max_batch=8 * (P - 2),
-                 audit=audit, min_archive=2 * P, rho_min=0.3, archive=16384, seed=seed,
-                 train_steps=8, lr=2e-3)
+                 audit=audit, min_archive=2 * P, rho_min=0.8, archive=16384, seed=seed,
+                 train_steps=48, lr=2e-3)
         screened = _best_after(gg, prob, G, sur=s, seed=seed)
-        st = s.stats()
-        assert st["screened_total"] > 0
+        trusted.append(s.stats()["screened_total"] / G)
         s.close()
         gains.append(plain / screened)
-    assert np.median(gains) > 1.0, gains
+    print("gains", gains, "trusted fractions", trusted)
+    assert np.median(gains) >= 1.25, gains
+    assert np.median(trusted) >= 0.5, trusted
 
 
 @pytest.mark.parametrize("population", [128, 1100])

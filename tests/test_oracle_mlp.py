@@ -92,3 +92,32 @@ def test_adam_training_reduces_loss():
         g = mlp.backward(params, X, t)
         params, m, v = mlp.adam_step(params, g, m, v, step, lr=1e-2)
     assert mlp.loss(params, X, t) < 0.3 * l0
+
+
+def test_input_stats_closed_forms():
+    """Per-gene standardisation of the network's inputs: a two-valued column
+    {a, b} (equal counts) has mean (a + b) / 2 and population deviation
+    |a - b| / 2; a constant column takes the floor; shifting a column moves
+    only its mean and scaling it by c scales its inverse deviation by 1/c;
+    the standardised columns have mean 0 and deviation 1."""
+    rng = np.random.default_rng(3)
+    rows = 1000
+    G = rng.uniform(-1, 1, (rows, 6))
+    G[:, 0] = np.where(np.arange(rows) % 2 == 0, 0.25, -0.75)    # two values
+    G[:, 1] = 0.5                                                # constant
+    G[:, 2] = 1e-4 * rng.standard_normal(rows)                   # below the floor
+    mean, inv = mlp.input_stats(G)
+    assert mean[0] == np.float32(-0.25) and inv[0] == np.float32(2.0)
+    assert mean[1] == np.float32(0.5) and inv[1] == np.float32(1.0 / mlp.INPUT_STD_FLOOR)
+    assert inv[2] == np.float32(1.0 / mlp.INPUT_STD_FLOOR)
+    m2, i2 = mlp.input_stats(np.column_stack([G[:, 3] + 0.125, 0.5 * G[:, 4]]))
+    np.testing.assert_allclose(m2[0], mean[3] + 0.125, rtol=1e-6)
+    np.testing.assert_allclose(i2[0], inv[3], rtol=1e-6)
+    np.testing.assert_allclose(i2[1], 2.0 * inv[4], rtol=1e-6)
+    X = mlp.standardize(G, mean, inv).astype(np.float64)
+    live = [0, 3, 4, 5]
+    np.testing.assert_allclose(X[:, live].mean(axis=0), 0.0, atol=1e-6)
+    np.testing.assert_allclose(X[:, live].std(axis=0), 1.0, rtol=1e-5)
+    # identity statistics leave the genes as they are
+    G32 = G.astype(np.float32)
+    assert np.array_equal(mlp.standardize(G32, np.zeros(6, np.float32), np.ones(6, np.float32)), G32)
