@@ -411,6 +411,26 @@ int game_batch_tune(game_batch_t b, int32_t tiles_per_item, int32_t grid);
 int game_batch_autotune(game_batch_t b, int32_t reps, int32_t* tiles_per_item, int32_t* grid,
                         float* best_ms, float* times_ms);
 
+/* Per-run work decomposition: run i's patterns are cut into items of
+ * tiles_per_item[i] (>= 1) 256-row tiles, host array [n_runs]; grid
+ * persistent fitness workgroups (1..65536).  Synchronises the stream. */
+int game_batch_tune_runs(game_batch_t b, const int32_t* tiles_per_item, int32_t grid);
+
+/* The decomposition in use: tiles_per_item [n_runs] (host) and the grid. */
+int game_batch_get_tuning(game_batch_t b, int32_t* tiles_per_item, int32_t* grid);
+
+/* The autotuner by shape bucket: run i belongs to bucket bucket_of_run[i]
+ * (0..n_buckets-1, n_buckets <= 64).  Starting from the best uniform
+ * decomposition (game_batch_autotune), each used bucket in turn tries every
+ * tiles_per_item of the uniform search with the other buckets fixed and
+ * keeps the fastest fitness launch (HIP events, reps launches each).  The
+ * result is set and returned: tiles_per_bucket [n_buckets] (host), the grid
+ * and its average launch time.  Leaves the populations as they were.
+ * Synchronises the stream. */
+int game_batch_autotune_buckets(game_batch_t b, int32_t reps, const int32_t* bucket_of_run,
+                                int32_t n_buckets, int32_t* tiles_per_bucket, int32_t* grid,
+                                float* best_ms);
+
 /* Generation 0 of every run (its own init_mode and seed). */
 int game_batch_init(game_batch_t b);
 
@@ -436,7 +456,8 @@ int game_batch_run(game_batch_t b, int32_t* generations_done_host, double* best_
 /* Current population [P x K] of one run and its last fitness [P]. */
 int game_batch_get_population(game_batch_t b, int32_t run, float* genes_dev, float* fitness_dev);
 
-/* Current work decomposition: number of items, tiles per item, grid. */
+/* Current work decomposition: number of items, tiles per item (0 when the
+ * runs' values differ), grid. */
 int game_batch_num_items(game_batch_t b, int32_t* n_items, int32_t* tiles_per_item, int32_t* grid);
 
 /* Message for the last failing call on this thread ("" if none). */

@@ -1313,7 +1313,8 @@ struct game_batch_ctx {
   int32_t n_ga_waves;
   int32_t max_pop;
   int32_t grid;
-  int32_t tiles_per_item;
+  int32_t tiles_per_item;         // the common value of run_tiles, or 0 when they differ
+  std::vector<int32_t> run_tiles; // patterns per item of each run, in 256-row tiles
   int32_t queue_begin[kXcds + 1];
   int32_t max_gen;
   size_t lds;
@@ -1385,10 +1386,10 @@ BatchLayout batch_layout(const game_run_desc* runs, int32_t n) {
   return L;
 }
 
-// Work decomposition: each run's patterns are cut into splits of about
-// `tiles` 256-row tiles; items are (run, chromosome tile, split), heaviest
+// Work decomposition: run r's patterns are cut into splits of about
+// tiles[r] 256-row tiles; items are (run, chromosome tile, split), heaviest
 // first so the queue ends with small items.
-int build_items(game_batch_ctx* b, int32_t tiles) {
+int build_items(game_batch_ctx* b, const std::vector<int32_t>& tiles_of_run) {
   // Groups: every chromosome tile of one (run, split), which read the same
   // patterns.  Dealt largest first to the least-loaded of the kXcds queues.
   struct Group {
@@ -1398,6 +1399,7 @@ int build_items(game_batch_ctx* b, int32_t tiles) {
   std::vector<Group> groups;
   for (int r = 0; r < b->n_runs; ++r) {
     BatchRun& run = b->runs[r];
+    const int tiles = tiles_of_run[r];
     int splits = (run.n_tiles + tiles - 1) / tiles;
     if (splits > kMaxSplits) splits = kMaxSplits;
     if (splits < 1) splits = 1;
@@ -1436,12 +1438,19 @@ int build_items(game_batch_ctx* b, int32_t tiles) {
                           hipMemcpyHostToDevice, b->stream));
   GAME_HIP(hipStreamSynchronize(b->stream));
   b->n_items = (int32_t)items.size();
-  b->tiles_per_item = tiles;
+  b->run_tiles = tiles_of_run;
+  b->tiles_per_item = tiles_of_run.empty() ? 0 : tiles_of_run[0];
+  for (const int32_t t : tiles_of_run)
+    if (t != b->tiles_per_item) b->tiles_per_item = 0;
   if (b->graph) {
     (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
   }
   return GAME_OK;
+}
+
+int build_items(game_batch_ctx* b, int32_t tiles) {
+  return build_items(b, std::vector<int32_t>(b->n_runs, tiles));
 }
 
 BatchArgs batch_args(const game_batch_ctx* b) {
@@ -1609,40 +1618,67 @@ int game_batch_tune(game_batch_t b, int32_t tiles_per_item, int32_t grid) {
   return build_items(b, tiles_per_item);
 }
 
+namespace {
+
+// Average duration (ms) of `reps` fitness launches of the current work list
+// after one untimed launch (HIP events on the batch's stream).
+int time_batch_fitness(game_batch_ctx* b, int32_t reps, hipEvent_t e0, hipEvent_t e1, float* ms) {
+  const BatchArgs a = batch_args(b);
+  hipError_t e = launch_batch_reset(a, b->stream);
+  if (e == hipSuccess) e = launch_fitness_batch(a, b->lds, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) {
+    e = launch_batch_reset(a, b->stream);
+    if (e == hipSuccess) e = launch_fitness_batch(a, b->lds, b->stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  if (e != hipSuccess) return hip_fail(e, "autotune launch");
+  *ms = t / reps;
+  return GAME_OK;
+}
+
+const int kTuneTiles[] = {1, 2, 4, 8, 16, 32, 64, 128};
+const int kTuneGrids[] = {256, 512, 1024};
+
+}  // namespace
+
+int game_batch_tune_runs(game_batch_t b, const int32_t* tiles_per_item, int32_t grid) {
+  if (!b || !tiles_per_item) return fail(GAME_EINVAL, "NULL argument");
+  if (grid < 1 || grid > 65536) return fail(GAME_EINVAL, "grid %d not in 1..65536", grid);
+  std::vector<int32_t> t(tiles_per_item, tiles_per_item + b->n_runs);
+  for (int r = 0; r < b->n_runs; ++r)
+    if (t[r] < 1) return fail(GAME_EINVAL, "run %d: tiles_per_item %d < 1", r, t[r]);
+  b->grid = grid;
+  return build_items(b, t);
+}
+
+int game_batch_get_tuning(game_batch_t b, int32_t* tiles_per_item, int32_t* grid) {
+  if (!b || !tiles_per_item) return fail(GAME_EINVAL, "NULL argument");
+  std::copy(b->run_tiles.begin(), b->run_tiles.end(), tiles_per_item);
+  if (grid) *grid = b->grid;
+  return GAME_OK;
+}
+
 int game_batch_autotune(game_batch_t b, int32_t reps, int32_t* best_tiles, int32_t* best_grid,
                         float* best_ms, float* times_ms) {
   if (!b) return fail(GAME_EINVAL, "batch is NULL");
   if (reps < 1) return fail(GAME_EINVAL, "reps < 1");
-  static const int kTiles[] = {1, 2, 4, 8, 16, 32, 64, 128};
-  static const int kGrids[] = {256, 512, 1024};
   hipEvent_t e0, e1;
   GAME_HIP(hipEventCreate(&e0));
   GAME_HIP(hipEventCreate(&e1));
   float best = 1e30f;
   int bt = 8, bg = 512, idx = 0;
   int rc = GAME_OK;
-  for (int tiles : kTiles) {
-    for (int grid : kGrids) {
+  for (int tiles : kTuneTiles) {
+    for (int grid : kTuneGrids) {
       b->grid = grid;
       rc = build_items(b, tiles);
-      if (rc) break;
-      const BatchArgs a = batch_args(b);
-      hipError_t e = launch_batch_reset(a, b->stream);
-      if (e == hipSuccess) e = launch_fitness_batch(a, b->lds, b->stream);
-      if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-      for (int i = 0; i < reps && e == hipSuccess; ++i) {
-        e = launch_batch_reset(a, b->stream);
-        if (e == hipSuccess) e = launch_fitness_batch(a, b->lds, b->stream);
-      }
-      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        rc = hip_fail(e, "autotune launch");
-        break;
-      }
-      ms /= reps;
+      if (!rc) rc = time_batch_fitness(b, reps, e0, e1, &ms);
+      if (rc) break;
       if (times_ms) times_ms[idx] = ms;
       ++idx;
       if (ms < best) {
@@ -1662,6 +1698,62 @@ int game_batch_autotune(game_batch_t b, int32_t reps, int32_t* best_tiles, int32
   GAME_HIP(launch_batch_reset(batch_args(b), b->stream));
   if (best_tiles) *best_tiles = bt;
   if (best_grid) *best_grid = bg;
+  if (best_ms) *best_ms = best;
+  return GAME_OK;
+}
+
+int game_batch_autotune_buckets(game_batch_t b, int32_t reps, const int32_t* bucket_of_run,
+                                int32_t n_buckets, int32_t* tiles_per_bucket, int32_t* grid,
+                                float* best_ms) {
+  if (!b || !bucket_of_run || !tiles_per_bucket) return fail(GAME_EINVAL, "NULL argument");
+  if (reps < 1) return fail(GAME_EINVAL, "reps < 1");
+  if (n_buckets < 1 || n_buckets > 64) return fail(GAME_EINVAL, "n_buckets not in 1..64");
+  for (int r = 0; r < b->n_runs; ++r)
+    if (bucket_of_run[r] < 0 || bucket_of_run[r] >= n_buckets)
+      return fail(GAME_EINVAL, "run %d: bucket %d not in 0..%d", r, bucket_of_run[r], n_buckets - 1);
+  int32_t t0 = 8, g0 = 512;
+  float best = 0.f;
+  int rc = game_batch_autotune(b, reps, &t0, &g0, &best, nullptr);
+  if (rc) return rc;
+  std::vector<int32_t> bt(n_buckets, t0);
+  auto runs_tiles = [&](const std::vector<int32_t>& per_bucket) {
+    std::vector<int32_t> t(b->n_runs);
+    for (int r = 0; r < b->n_runs; ++r) t[r] = per_bucket[bucket_of_run[r]];
+    return t;
+  };
+  hipEvent_t e0, e1;
+  GAME_HIP(hipEventCreate(&e0));
+  GAME_HIP(hipEventCreate(&e1));
+  b->grid = g0;
+  rc = build_items(b, runs_tiles(bt));
+  if (!rc) rc = time_batch_fitness(b, reps, e0, e1, &best);
+  for (int k = 0; k < n_buckets && !rc; ++k) {
+    bool used = false;
+    for (int r = 0; r < b->n_runs; ++r) used = used || bucket_of_run[r] == k;
+    if (!used) continue;
+    const int32_t keep = bt[k];
+    for (int tiles : kTuneTiles) {
+      if (tiles == keep) continue;
+      std::vector<int32_t> trial = bt;
+      trial[k] = tiles;
+      rc = build_items(b, runs_tiles(trial));
+      float ms = 0.f;
+      if (!rc) rc = time_batch_fitness(b, reps, e0, e1, &ms);
+      if (rc) break;
+      if (ms < best) {
+        best = ms;
+        bt = trial;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  rc = build_items(b, runs_tiles(bt));
+  if (rc) return rc;
+  GAME_HIP(launch_batch_reset(batch_args(b), b->stream));
+  std::copy(bt.begin(), bt.end(), tiles_per_bucket);
+  if (grid) *grid = g0;
   if (best_ms) *best_ms = best;
   return GAME_OK;
 }

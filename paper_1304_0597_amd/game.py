@@ -108,6 +108,10 @@ _SIGS = {
                                     POINTER(c_void_p)]),
     "game_batch_destroy": (c_int32, [c_void_p]),
     "game_batch_tune": (c_int32, [c_void_p, c_int32, c_int32]),
+    "game_batch_tune_runs": (c_int32, [c_void_p, c_void_p, c_int32]),
+    "game_batch_get_tuning": (c_int32, [c_void_p, c_void_p, POINTER(c_int32)]),
+    "game_batch_autotune_buckets": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p,
+                                              POINTER(c_int32), POINTER(c_float)]),
     "game_batch_autotune": (c_int32, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32),
                                       POINTER(c_float), c_void_p]),
     "game_batch_init": (c_int32, [c_void_p]),
@@ -541,7 +545,7 @@ def game_batch_create(descs, n_runs, workspace, stream=None) -> int:
     _check(lib().game_batch_create(descs, n_runs, _ptr(workspace),
                                    workspace.numel() * workspace.element_size(), _stream(stream),
                                    ctypes.byref(h)))
-    _handles[h.value] = {"runs": runs}
+    _handles[h.value] = {"runs": runs, "n_runs": n_runs}
     return h.value
 
 
@@ -552,6 +556,32 @@ def game_batch_destroy(b) -> None:
 
 def game_batch_tune(b, tiles_per_item, grid) -> None:
     _check(lib().game_batch_tune(b, tiles_per_item, grid))
+
+
+def game_batch_tune_runs(b, tiles_per_item, grid) -> None:
+    t = np.ascontiguousarray(tiles_per_item, dtype=np.int32)
+    if t.ndim != 1 or t.size != _dims(b)["n_runs"]:
+        raise ValueError(f"tiles_per_item: expected {_dims(b)['n_runs']} values, got {t.size}")
+    _check(lib().game_batch_tune_runs(b, t.ctypes.data_as(c_void_p), grid))
+
+
+def game_batch_get_tuning(b) -> tuple:
+    t = np.zeros(_dims(b)["n_runs"], dtype=np.int32)
+    g = c_int32()
+    _check(lib().game_batch_get_tuning(b, t.ctypes.data_as(c_void_p), ctypes.byref(g)))
+    return t, g.value
+
+
+def game_batch_autotune_buckets(b, bucket_of_run, n_buckets, reps=3) -> dict:
+    k = np.ascontiguousarray(bucket_of_run, dtype=np.int32)
+    if k.ndim != 1 or k.size != _dims(b)["n_runs"]:
+        raise ValueError(f"bucket_of_run: expected {_dims(b)['n_runs']} values, got {k.size}")
+    out = np.zeros(n_buckets, dtype=np.int32)
+    g, ms = c_int32(), c_float()
+    _check(lib().game_batch_autotune_buckets(b, reps, k.ctypes.data_as(c_void_p), n_buckets,
+                                             out.ctypes.data_as(c_void_p), ctypes.byref(g),
+                                             ctypes.byref(ms)))
+    return {"tiles_per_bucket": [int(v) for v in out], "grid": g.value, "ms": ms.value}
 
 
 def game_batch_autotune(b, reps=3) -> dict:
@@ -633,6 +663,15 @@ class Batch:
 
     def autotune(self, reps=3):
         return game_batch_autotune(self.h, reps)
+
+    def tune_runs(self, tiles_per_item, grid):
+        game_batch_tune_runs(self.h, tiles_per_item, grid)
+
+    def tuning(self):
+        return game_batch_get_tuning(self.h)
+
+    def autotune_buckets(self, bucket_of_run, n_buckets, reps=3):
+        return game_batch_autotune_buckets(self.h, bucket_of_run, n_buckets, reps)
 
     def init(self):
         game_batch_init(self.h)

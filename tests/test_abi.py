@@ -198,3 +198,14 @@ def test_autotune_candidate_count_matches_header():
     src = open(HEADER).read()
     n = int(re.search(r"#define\s+GAME_AUTOTUNE_CANDIDATES\s+(\d+)", src).group(1))
     assert n == len(game.AUTOTUNE_TILES) * len(game.AUTOTUNE_GRIDS)
+
+
+def test_batch_shape_buckets():
+    """Runs are bucketed by their expansion terms K - 1 (bounds 32, 64, 128,
+    256, then open); the table maps each run to its bucket's value."""
+    from paper_1304_0597_amd import batch_tuning as bt
+    assert [bt.bucket_of(k) for k in (2, 33, 34, 65, 66, 129, 130, 257, 258, 4097)] == \
+        [0, 0, 1, 1, 2, 2, 3, 3, 4, 4]
+    table = {"tiles_per_bucket": [1, 2, 4, 8, 16]}
+    assert bt.tiles_for(table, [9, 60, 100, 200, 641]) == [1, 2, 4, 8, 16]
+    assert bt.N_BUCKETS == len(table["tiles_per_bucket"])

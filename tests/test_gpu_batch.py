@@ -141,6 +141,42 @@ def test_any_decomposition_gives_the_same_trajectory(gg, tiles, grid):
     b2.close()
 
 
+def test_per_run_decomposition_and_bucketed_autotuner(gg):
+    """Per-run items sizes (game_batch_tune_runs) and the bucketed autotuner
+    keep every run on the trajectory of the default decomposition, bit for
+    bit; the autotuner's choice is set and reported back."""
+    from paper_1304_0597_amd import batch_tuning
+    problems, cfgs, _ = make_runs(gg)
+    ref = gg.Batch(problems, cfgs)
+    ref.init()
+    for _ in range(3):
+        ref.step()
+    b = gg.Batch(problems, cfgs)
+    tiles = [1, 3, 8, 2, 16, 5]
+    b.tune_runs(tiles, 300)
+    got, grid = b.tuning()
+    assert list(got) == tiles and grid == 300 and b.items()[1] == 0
+    b.init()
+    b.step()
+    buckets = [batch_tuning.bucket_of(k) for k in b.n_genes]
+    res = b.autotune_buckets(buckets, batch_tuning.N_BUCKETS, reps=1)
+    got, grid = b.tuning()
+    assert list(got) == [res["tiles_per_bucket"][k] for k in buckets]
+    assert grid == res["grid"] and res["ms"] > 0
+    assert all(t in gg.AUTOTUNE_TILES for t in res["tiles_per_bucket"])
+    b.step()
+    b.step()
+    for r in range(b.n_runs):
+        assert np.array_equal(bits(b.population(r)[0].cpu().numpy()),
+                              bits(ref.population(r)[0].cpu().numpy()))
+    with pytest.raises(ValueError):
+        b.tune_runs(tiles[:-1], 300)
+    with pytest.raises(gg.GameError):
+        b.tune_runs([0] * len(tiles), 300)
+    b.close()
+    ref.close()
+
+
 def test_batched_workload_sample(gg):
     """The first 12 runs of the 256-run batched workload recipe at full size;
     fitness of two runs checked against the oracle on sampled chromosomes."""
