@@ -598,6 +598,26 @@ def form_batched(gg, steps, warmup, decomposition=None, autotune=False):
             "decomposition": dict(dec, items=n_items)}
 
 
+def calibrate_gemm(reps=20):
+    """The vendor library's BF16 GEMM (torch.matmul -> hipBLASLt, FP32
+    accumulation) on two large shapes and on the fitness contraction's own
+    shape (131,072 x 4,096 x 256): median TFLOP/s over HIP-event-timed
+    launches.  A reference for what the matrix cores sustain on this GPU,
+    not a part of the method."""
+    import torch
+    out = {}
+    stream = torch.cuda.current_stream()
+    for (M, N, K) in ((8192, 8192, 8192), (16384, 16384, 8192), (131072, 4096, 256)):
+        a = torch.randn(M, K, dtype=torch.bfloat16, device="cuda:0")
+        b = torch.randn(K, N, dtype=torch.bfloat16, device="cuda:0")
+        t = time_median(lambda: torch.matmul(a, b), stream, reps=reps)
+        tf = 2.0 * M * N * K / t / 1e12
+        out[f"{M}x{N}x{K}"] = {"ms": t * 1e3, "tflops": tf, "frac": tf / BF16_MFMA_PEAK_TFLOPS}
+        del a, b
+    return {"calibration": "torch.matmul bfloat16 (hipBLASLt)", "peak_tflops": BF16_MFMA_PEAK_TFLOPS,
+            "shapes": out}
+
+
 def scale_step(gg, prob, steps, warmup):
     """The headline line: generations of the scale workload, and its fused
     fitness kernel on the MFMA roofline."""
@@ -653,6 +673,9 @@ def main():
                     help="batched form: a uniform 'tiles,grid' instead of the committed table")
     ap.add_argument("--batch-autotune", action="store_true",
                     help="batched form: run the uniform autotuner instead of the committed table")
+    ap.add_argument("--calibrate-gemm", action="store_true",
+                    help="only time the vendor BF16 GEMM (torch.matmul, hipBLASLt) on large "
+                         "square-ish shapes: the practical matrix-core throughput of this GPU")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise kernel of known traffic (256 MiB read, "
                          "256 MiB written per launch) to scale hardware byte counters")
@@ -671,6 +694,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "torch.neg float32", "bytes_read": x.numel() * 4,
                           "bytes_written": y.numel() * 4, "launches": 5}), flush=True)
+        return
+    if args.calibrate_gemm:
+        print(json.dumps(calibrate_gemm()), flush=True)
         return
     from paper_1304_0597_amd import datagen
     from paper_1304_0597_amd import game as gg
