@@ -203,3 +203,39 @@ def test_precision_shape_fp32_sampled(gg):
     ok = within(f64[idx], ref, prob.t)
     assert ok.all(), np.max(np.abs(f64[idx] - ref) / ref)
     assert np.array_equal(f32, f64.astype(np.float32))
+
+
+@pytest.mark.parametrize("shape", [(3001, 20, 4, 130), (300, 33, 10, 70), (8000, 33, 10, 1100)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_trig_table_gives_the_kernels_own_bits(gg, shape):
+    """A float32 trig run seeds the recurrence from the (cos x, sin x) table
+    computed once at game_create; the same chromosomes evaluated on a copy
+    of the patterns (another address, so no table) seed it with sincosf in
+    every tile.  The float64 errors are bit-identical, and the batched form
+    (sincosf in its kernel) gives them too."""
+    NP, N, d, P = shape
+    X, t, W = problem(NP, N, d, P, 3, seed=NP + N)
+    cfg = gg.config(basis=3, degree=d, population=P, tournament_k=3, elitism=1)
+    Xd, td = torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda()
+    g = gg.Game(cfg, Xd, td)
+    Wd = torch.from_numpy(W).cuda()
+    _, f_table = g.fitness(Wd, with64=True)
+    f_copy = g.evaluate(Xd.clone(), td, Wd)
+    torch.cuda.synchronize()
+    a, b = f_table.cpu().numpy(), f_copy.cpu().numpy()
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    assert within(a, og.fitness(X, t, W, 3, d), t).all()
+    g.close()
+    batch = gg.Batch([(Xd, td)], [cfg])
+    gg.game_batch_tune(batch.h, 2, 64)
+    batch.init()
+    pop, _ = batch.population(0)
+    g2 = gg.Game(cfg, Xd, td)
+    _, f_pop = g2.fitness(pop.contiguous(), with64=True)
+    batch.evaluate()
+    _, f_batch = batch.population(0)
+    torch.cuda.synchronize()
+    assert np.array_equal(f_batch.cpu().numpy().view(np.uint32),
+                          f_pop.cpu().numpy().astype(np.float32).view(np.uint32))
+    g2.close()
+    batch.close()
