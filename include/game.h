@@ -390,9 +390,14 @@ size_t game_batch_workspace_size(const game_run_desc* runs, int32_t n_runs);
 
 /* Creates a batch over caller-owned data; the workspace (256-byte aligned,
  * game_batch_workspace_size bytes) holds every run's populations, fitness,
- * partial sums and the work list.  Copies the descriptors; synchronises
- * the stream once.  The default decomposition is 8 tiles of 256 patterns
- * per item and 512 persistent workgroups. */
+ * partial sums and the work list, and for each run of the trigonometric
+ * expansion (Eq. 8) cos x and sin x of its patterns (n_patterns x
+ * n_features x 8 bytes), computed here once.  X_dev and t_dev of every run
+ * must stay valid and unchanged until game_batch_destroy.  Copies the
+ * descriptors; synchronises the stream once.  The default decomposition is
+ * 8 tiles of 256 patterns per item and 512 persistent workgroups.  The
+ * fitness of a generation is one persistent launch for the polynomial
+ * families and one for the trigonometric runs, if any. */
 int game_batch_create(const game_run_desc* runs, int32_t n_runs, void* workspace_dev,
                       size_t workspace_bytes, void* hip_stream, game_batch_t* out);
 int game_batch_destroy(game_batch_t b);

@@ -214,6 +214,7 @@ hipError_t launch_set_state(RunState* st, int32_t gen, int32_t max_gen, double t
 struct BatchRun {
   const float* X;
   const float* t;
+  const float* cs;          // trigonometric runs: (cos x, sin x) per pattern and feature
   int64_t NP;
   int32_t N;
   int32_t K;
@@ -260,15 +261,19 @@ struct BatchItem {
   int32_t cost;             // relative work, for ordering
 };
 
-// The batched fitness work list is split into one queue per XCD (8 on
+// The batched fitness work list is split by expansion family, one launch per
+// family present, and each family's items into one queue per XCD (8 on
 // MI355X); workgroup b starts on queue b % 8, the XCD the hardware dispatches
-// it to, and takes work from the other queues once its own is empty.
+// it to, and takes work from the family's other queues once its own is empty.
 constexpr int kXcds = 8;
+constexpr int kFamilies = 4;
+constexpr int kQueues = kFamilies * kXcds;  // queue f * kXcds + q: family f, XCD q
+static_assert(kQueues <= 64, "the queue heads are re-armed by one wave");
 
 struct BatchArgs {
   const BatchRun* runs;
   const BatchItem* items;
-  int32_t* counter;         // kXcds queue heads of the fitness launch
+  int32_t* counter;         // kQueues queue heads of the fitness launches
   const int32_t* rank_block_run;
   const int32_t* ga_wave_run;
   int32_t n_runs;
@@ -277,7 +282,7 @@ struct BatchArgs {
   int32_t n_ga_waves;
   int32_t max_population;
   int32_t grid;             // persistent fitness workgroups
-  int32_t queue_begin[kXcds + 1];  // queue q holds items [queue_begin[q], queue_begin[q+1])
+  int32_t queue_begin[kQueues + 1];  // queue q holds items [queue_begin[q], queue_begin[q+1])
 };
 hipError_t launch_fitness_batch(const BatchArgs& a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_finish_rank_batch(const BatchArgs& a, hipStream_t s);

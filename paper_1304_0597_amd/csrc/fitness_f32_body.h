@@ -47,17 +47,12 @@ __device__ __forceinline__ gptr_f32 global_f32(const float* p) { return (gptr_f3
 // chromosomes being scored; lds: the workgroup's dynamic LDS.  D is the
 // degree.  BASIS is the expansion family (kTrigTable: the trigonometric one
 // seeded from the stored (cos x, sin x) table a_in.cs instead of sincosf in
-// every tile), or -1 for the family a_in.basis
-// read at run time: the same K-steps in the same order, each recurrence step
-// the table-driven form of Recur<-1> with the bits of the fixed family's, so
-// both forms give the same bits (the batched kernel runs every run's family
-// through one body per degree this way).
+// every tile).
 template <int BASIS, int D>
 __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const float* __restrict__ genes,
                                                   int split, int ctile, float* lds) {
-  // The parameters the body uses, read once into scalar registers.  (In the
-  // batched kernel a_in sits in private memory behind a generic pointer that
-  // any store might alias; left there, the loops would reload it.)
+  // The parameters the body uses, read once into scalar registers (so that
+  // no store in the loops can be taken to alias them and force reloads).
   FitArgs a;
   a.X = uniform(a_in.X);
   a.t = uniform(a_in.t);
@@ -76,12 +71,12 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   a.error_fn = uniform(a_in.error_fn);
   a.R = uniform(a_in.R);
   constexpr bool kTable = BASIS == kTrigTable;
-  constexpr int FAM = kTable ? 3 : BASIS;   // expansion family (-1: run time)
+  constexpr int FAM = kTable ? 3 : BASIS;   // expansion family
+  static_assert(FAM >= 0 && FAM <= 3, "compile-time expansion family");
   a.cs = kTable ? uniform(a_in.cs) : nullptr;
   static_assert(D >= 1 && D <= kMaxDegree, "compile-time degree");
   constexpr int Dv = D;
-  const int fam = FAM >= 0 ? FAM : uniform(a_in.basis);
-  const bool trig = fam == 3;
+  constexpr bool trig = FAM == 3;
   genes = uniform(genes);
   split = uniform(split);
   ctile = uniform(ctile);
@@ -222,9 +217,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
         Recur<FAM> rc[2];
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
-          if constexpr (FAM < 0) {
-            rc[rb].seed(fam, x[rb], h);
-          } else if constexpr (kTable) {
+          if constexpr (kTable) {
             rc[rb].seed_cs(x[rb], sx[rb], h);
           } else {
             rc[rb].seed(x[rb], h);
@@ -246,8 +239,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
           if constexpr (j + 1 < D) {
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb) {
-              if constexpr (FAM < 0) rc[rb].template advance_fam<j + 1>(fam);
-              else rc[rb].template advance<j + 1>(x[rb]);
+              rc[rb].template advance<j + 1>(x[rb]);
             }
           }
         };

@@ -514,7 +514,7 @@ hipError_t launch_finish_rank_batch(const BatchArgs& a, hipStream_t s) {
 // Genetic-step waves of every run in one launch; also re-arms the fitness
 // work queue for the next generation.
 __global__ __launch_bounds__(256) void ga_next_batch_kernel(BatchArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x < kXcds) a.counter[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kQueues) a.counter[threadIdx.x] = 0;
   const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (gw >= a.n_ga_waves) return;
   const int r = a.ga_wave_run[gw];
@@ -569,7 +569,7 @@ hipError_t launch_roulette_cum_batch(const BatchArgs& a, hipStream_t s) {
 }
 
 __global__ void batch_reset_kernel(BatchArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x < kXcds) a.counter[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kQueues) a.counter[threadIdx.x] = 0;
 }
 
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s) {

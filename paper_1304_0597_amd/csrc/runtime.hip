@@ -1315,7 +1315,7 @@ struct game_batch_ctx {
   int32_t grid;
   int32_t tiles_per_item;         // the common value of run_tiles, or 0 when they differ
   std::vector<int32_t> run_tiles; // patterns per item of each run, in 256-row tiles
-  int32_t queue_begin[kXcds + 1];
+  int32_t queue_begin[kQueues + 1];
   int32_t max_gen;
   size_t lds;
   hipStream_t stream;
@@ -1332,7 +1332,7 @@ namespace {
 
 struct BatchLayout {
   size_t runs, items, counter, rank_map, ga_map, states, total;
-  std::vector<size_t> pop0, pop1, fit32, fit64, order, cum, partial;
+  std::vector<size_t> pop0, pop1, fit32, fit64, order, cum, partial, cs;
   int64_t item_capacity;
   int32_t n_rank_blocks, n_ga_waves;
 };
@@ -1366,7 +1366,7 @@ BatchLayout batch_layout(const game_run_desc* runs, int32_t n) {
   size_t off = 0;
   L.runs = off; off += align_up(sizeof(BatchRun) * n);
   L.items = off; off += align_up(sizeof(BatchItem) * cap);
-  L.counter = off; off += align_up(sizeof(int32_t) * kXcds);
+  L.counter = off; off += align_up(sizeof(int32_t) * kQueues);
   L.rank_map = off; off += align_up(sizeof(int32_t) * rb);
   L.ga_map = off; off += align_up(sizeof(int32_t) * gw);
   L.states = off; off += align_up(sizeof(RunState) * n);
@@ -1381,6 +1381,9 @@ BatchLayout batch_layout(const game_run_desc* runs, int32_t n) {
     L.order.push_back(off); off += align_up(P * sizeof(int32_t));
     L.cum.push_back(off); off += align_up(P * sizeof(double));
     L.partial.push_back(off); off += align_up(Ppad * kMaxSplits * sizeof(double));
+    L.cs.push_back(off);
+    if (runs[i].cfg.basis == GAME_TRIG)
+      off += align_up((size_t)runs[i].n_patterns * runs[i].n_features * 2 * sizeof(float));
   }
   L.total = off;
   return L;
@@ -1391,7 +1394,8 @@ BatchLayout batch_layout(const game_run_desc* runs, int32_t n) {
 // first so the queue ends with small items.
 int build_items(game_batch_ctx* b, const std::vector<int32_t>& tiles_of_run) {
   // Groups: every chromosome tile of one (run, split), which read the same
-  // patterns.  Dealt largest first to the least-loaded of the kXcds queues.
+  // patterns.  Dealt largest first to the least-loaded of the kXcds queues
+  // of the run's expansion family (one fitness launch per family).
   struct Group {
     int32_t run, split;
     int64_t cost;
@@ -1412,15 +1416,16 @@ int build_items(game_batch_ctx* b, const std::vector<int32_t>& tiles_of_run) {
   }
   std::stable_sort(groups.begin(), groups.end(),
                    [](const Group& x, const Group& y) { return x.cost > y.cost; });
-  std::vector<std::vector<int32_t>> dealt(kXcds);
-  int64_t load[kXcds] = {};
+  std::vector<std::vector<int32_t>> dealt(kQueues);
+  int64_t load[kQueues] = {};
   for (int32_t g = 0; g < (int32_t)groups.size(); ++g) {
-    const int q = (int)(std::min_element(load, load + kXcds) - load);
+    int64_t* fam = load + b->runs[groups[g].run].basis * kXcds;
+    const int q = (int)(std::min_element(fam, fam + kXcds) - load);
     dealt[q].push_back(g);
     load[q] += groups[g].cost;
   }
   std::vector<BatchItem> items;
-  for (int q = 0; q < kXcds; ++q) {
+  for (int q = 0; q < kQueues; ++q) {
     b->queue_begin[q] = (int32_t)items.size();
     for (const int32_t g : dealt[q]) {
       const BatchRun& run = b->runs[groups[g].run];
@@ -1430,7 +1435,7 @@ int build_items(game_batch_ctx* b, const std::vector<int32_t>& tiles_of_run) {
         items.push_back({groups[g].run, c, groups[g].split, rows * run.Q * run.D});
     }
   }
-  b->queue_begin[kXcds] = (int32_t)items.size();
+  b->queue_begin[kQueues] = (int32_t)items.size();
   if ((int64_t)items.size() > b->item_capacity) return fail(GAME_EINVAL, "too many items");
   GAME_HIP(hipMemcpyAsync(b->items_dev, items.data(), sizeof(BatchItem) * items.size(),
                           hipMemcpyHostToDevice, b->stream));
@@ -1466,7 +1471,7 @@ BatchArgs batch_args(const game_batch_ctx* b) {
   a.n_ga_waves = b->n_ga_waves;
   a.max_population = b->max_pop;
   a.grid = b->grid;
-  for (int q = 0; q <= kXcds; ++q) a.queue_begin[q] = b->queue_begin[q];
+  for (int q = 0; q <= kQueues; ++q) a.queue_begin[q] = b->queue_begin[q];
   return a;
 }
 
@@ -1557,6 +1562,7 @@ int game_batch_create(const game_run_desc* runs, int32_t n_runs, void* ws, size_
     r.fit64 = (double*)(base + L.fit64[i]);
     r.order = (int32_t*)(base + L.order[i]);
     r.partial = (double*)(base + L.partial[i]);
+    r.cs = c.basis == GAME_TRIG ? (const float*)(base + L.cs[i]) : nullptr;
     r.state = b->states + i;
     r.P = c.population;
     r.k = c.tournament_k;
@@ -1588,6 +1594,14 @@ int game_batch_create(const game_run_desc* runs, int32_t n_runs, void* ws, size_
       e = hipMemcpyAsync(b->ga_wave_run, ga_map.data(), sizeof(int32_t) * ga_map.size(),
                          hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) rc = hip_fail(e, "hipMemcpyAsync");
+  }
+  // (cos x, sin x) of every pattern and feature of the trigonometric runs,
+  // once for the batch's lifetime (the data sets do not change).
+  for (int i = 0; i < n_runs && !rc; ++i) {
+    const BatchRun& r = b->runs[i];
+    if (!r.cs) continue;
+    e = launch_trig_cs(r.X, r.NP, r.N, const_cast<float*>(r.cs), b->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "launch_trig_cs");
   }
   if (!rc) rc = create_chunk_sync(n_runs, &b->host_states, b->chunk_done);
   if (!rc) rc = build_items(b, 8);
