@@ -209,7 +209,7 @@ SURROGATE_CFG = dict(hidden=256, fp32_operands=0, archive=16384, minibatch=1024,
 
 
 def _run_to_target(gg, prob, precision, cap, val_target=None, train_target=None,
-                   surrogate=None, seed=0, chunk=5, split_at=None):
+                   surrogate=None, seed=0, chunk=5, split_at=None, trace_every=None):
     """One GA run on the precision problem from generation 0.
 
     With val_target None the run takes exactly `cap` generations (the plain
@@ -220,7 +220,9 @@ def _run_to_target(gg, prob, precision, cap, val_target=None, train_target=None,
     set, stopping once that is <= val_target or after `cap` generations.
     Wall time covers initialisation, graph capture, the generations, the
     surrogate's training and the validation checks.  The first time the
-    best training error is <= train_target is recorded too."""
+    best training error is <= train_target is recorded too.  With
+    trace_every, every that many generations the best's float64 validation
+    error is recorded (and a progress line logged)."""
     import torch
     dev = torch.device("cuda:0")
     P = prob.population
@@ -243,13 +245,26 @@ def _run_to_target(gg, prob, precision, cap, val_target=None, train_target=None,
     game.init_population()
     reached_val = reached_train = None
     split = None
+    trace = []
+
+    def traced(gens, best):
+        if trace_every and gens % trace_every == 0:
+            trace.append({"generation": gens, "seconds": time.perf_counter() - t0,
+                          "validation_mse_fp64": val_of(best)})
+            log(f"  generation {gens}: validation {trace[-1]['validation_mse_fp64']:.5f}")
+
     if val_target is None:
         if split_at is not None:
             g1, best1, err1 = game.run(max_generations=split_at)
             split = {"generations": g1, "seconds": time.perf_counter() - t0,
                      "train_mse_fp64": float(game.rescore64(
                          torch.from_numpy(best1).to(dev).view(1, -1))[0])}
-        gens, best, err = game.run(max_generations=cap)
+        step = trace_every or cap
+        gen = 0
+        while gen < cap:
+            gen = min(gen + step, cap)
+            gens, best, err = game.run(max_generations=gen)
+            traced(gens, best)
     else:
         gen = 0
         while True:
@@ -260,6 +275,7 @@ def _run_to_target(gg, prob, precision, cap, val_target=None, train_target=None,
             if val_of(best) <= val_target:
                 reached_val = {"generations": gens, "seconds": time.perf_counter() - t0}
                 break
+            traced(gens, best)
             if gens >= cap:
                 break
     elapsed = time.perf_counter() - t0
@@ -277,6 +293,8 @@ def _run_to_target(gg, prob, precision, cap, val_target=None, train_target=None,
         res["reached_train_target"] = reached_train
     if split is not None:
         res["at_split"] = split
+    if trace:
+        res["validation_trace"] = trace
     if sur is not None:
         st = sur.stats()
         res["surrogate"] = {"last_rho": st["rho"], "screened_generations": st["screened_total"],
@@ -413,6 +431,40 @@ def form_time_to_target(gg, prob, reference_generations=1000, secondary_generati
         "target_validation_mse", "secondary_target_train_mse", "plain_fp32", "plain_bf16",
         "surrogate_bf16", "untrained_surrogate_bf16")}})
     return out
+
+
+def form_long_horizon(gg, prob, generations=5000, seed=0, cap=3, surrogate_cfg=None):
+    """The time-to-target comparison at a later target, one seed: plain
+    float32 GAME runs `generations` generations (its best's float64
+    validation error every 1,000 generations is recorded) and the final one
+    is T*; plain BF16 and surrogate + BF16 then run until their best's
+    float64 validation error is <= T*, at most `cap` times as many
+    generations.  Shows whether the surrogate's lead holds further down the
+    descent than the 1,000-generation target."""
+    sur_cfg = dict(surrogate_cfg or SURROGATE_CFG)
+    log(f"long horizon: plain FP32, {generations} generations (seed {seed})")
+    plain = _run_to_target(gg, prob, gg.GAME_FP32, generations, seed=seed, trace_every=1000)
+    T = plain["validation_mse_fp64"]
+    cap_g = cap * generations
+    log(f"long horizon: T* = {T:.5f}; plain BF16")
+    bf16 = _run_to_target(gg, prob, gg.GAME_BF16, cap_g, val_target=T, seed=seed,
+                          trace_every=1000)
+    log("long horizon: surrogate + BF16")
+    chosen = _run_to_target(gg, prob, gg.GAME_BF16, cap_g, val_target=T, surrogate=sur_cfg,
+                            seed=seed, trace_every=1000)
+    return {"workload": "precision problem (1,000,000 x 32, Chebyshev degree 8, population "
+                        f"4,096, validation 250,000 patterns), GA seed {seed}; target T* = "
+                        f"float64 validation error of plain FP32's best after {generations} "
+                        "generations; the other forms stop once their best's float64 "
+                        f"validation error is <= T* (checked every 5 generations, at most "
+                        f"{cap_g} generations)",
+            "target_validation_mse": T,
+            # the error of the best constant predictor on the validation set
+            "validation_target_variance": float(np.var(prob.t_val.astype(np.float64))),
+            "plain_fp32": plain, "plain_bf16": bf16, "surrogate_bf16": chosen,
+            "speedup_chosen_vs_plain_fp32": (plain["seconds"] / chosen["seconds"]
+                                             if chosen["reached"] else None),
+            "surrogate_config": sur_cfg}
 
 
 # Whole-training wall time (TOT, seconds) of the paper's GPU version for
@@ -598,24 +650,30 @@ def form_batched(gg, steps, warmup, decomposition=None, autotune=False):
             "decomposition": dict(dec, items=n_items)}
 
 
-def calibrate_gemm(reps=20):
-    """The vendor library's BF16 GEMM (torch.matmul -> hipBLASLt, FP32
-    accumulation) on two large shapes and on the fitness contraction's own
-    shape (131,072 x 4,096 x 256): median TFLOP/s over HIP-event-timed
-    launches.  A reference for what the matrix cores sustain on this GPU,
-    not a part of the method."""
+def calibrate_gemm(reps=20, fp32=False):
+    """The vendor library's GEMM (torch.matmul -> hipBLASLt) on two large
+    shapes and on the fitness contraction's own shape: median TFLOP/s over
+    HIP-event-timed launches.  BF16 operands with FP32 accumulation on
+    131,072 x 4,096 x 256 (the precision workload), or, with fp32, float32
+    operands (TF32 off) on 200,000 x 2,048 x 160 (the scale workload).  A
+    reference for what the matrix cores sustain on this GPU, not a part of
+    the method."""
     import torch
+    torch.backends.cuda.matmul.allow_tf32 = False
+    dtype = torch.float32 if fp32 else torch.bfloat16
+    peak = FP32_MFMA_PEAK_TFLOPS if fp32 else BF16_MFMA_PEAK_TFLOPS
+    own = (200_000, 2048, 160) if fp32 else (131072, 4096, 256)
     out = {}
     stream = torch.cuda.current_stream()
-    for (M, N, K) in ((8192, 8192, 8192), (16384, 16384, 8192), (131072, 4096, 256)):
-        a = torch.randn(M, K, dtype=torch.bfloat16, device="cuda:0")
-        b = torch.randn(K, N, dtype=torch.bfloat16, device="cuda:0")
+    for (M, N, K) in ((8192, 8192, 8192), (16384, 16384, 8192), own):
+        a = torch.randn(M, K, dtype=dtype, device="cuda:0")
+        b = torch.randn(K, N, dtype=dtype, device="cuda:0")
         t = time_median(lambda: torch.matmul(a, b), stream, reps=reps)
         tf = 2.0 * M * N * K / t / 1e12
-        out[f"{M}x{N}x{K}"] = {"ms": t * 1e3, "tflops": tf, "frac": tf / BF16_MFMA_PEAK_TFLOPS}
+        out[f"{M}x{N}x{K}"] = {"ms": t * 1e3, "tflops": tf, "frac": tf / peak}
         del a, b
-    return {"calibration": "torch.matmul bfloat16 (hipBLASLt)", "peak_tflops": BF16_MFMA_PEAK_TFLOPS,
-            "shapes": out}
+    return {"calibration": f"torch.matmul {'float32' if fp32 else 'bfloat16'} (hipBLASLt)",
+            "peak_tflops": peak, "shapes": out}
 
 
 def scale_step(gg, prob, steps, warmup):
@@ -667,7 +725,10 @@ def main():
                     help="generations of the plain FP32 run that sets the time-to-target goal")
     ap.add_argument("--target-seeds", type=int, default=5,
                     help="GA seeds of the time-to-target comparison (0, 1, ...)")
-    ap.add_argument("--only", choices=["scale", "bf16", "batched", "target", "paper", "trig"],
+    ap.add_argument("--long-generations", type=int, default=5000,
+                    help="--only long_target: generations of the plain FP32 reference run")
+    ap.add_argument("--only", choices=["scale", "bf16", "batched", "target", "paper", "trig",
+                                       "long_target"],
                     help="run one workload alone and print its result (for profiling)")
     ap.add_argument("--batch-decomp", type=str, default=None,
                     help="batched form: a uniform 'tiles,grid' instead of the committed table")
@@ -676,6 +737,8 @@ def main():
     ap.add_argument("--calibrate-gemm", action="store_true",
                     help="only time the vendor BF16 GEMM (torch.matmul, hipBLASLt) on large "
                          "square-ish shapes: the practical matrix-core throughput of this GPU")
+    ap.add_argument("--calibrate-gemm-fp32", action="store_true",
+                    help="the same with float32 operands (TF32 off), against the FP32 MFMA peak")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain elementwise kernel of known traffic (256 MiB read, "
                          "256 MiB written per launch) to scale hardware byte counters")
@@ -695,15 +758,15 @@ def main():
         print(json.dumps({"calibration": "torch.neg float32", "bytes_read": x.numel() * 4,
                           "bytes_written": y.numel() * 4, "launches": 5}), flush=True)
         return
-    if args.calibrate_gemm:
-        print(json.dumps(calibrate_gemm()), flush=True)
+    if args.calibrate_gemm or args.calibrate_gemm_fp32:
+        print(json.dumps(calibrate_gemm(fp32=args.calibrate_gemm_fp32)), flush=True)
         return
     from paper_1304_0597_amd import datagen
     from paper_1304_0597_amd import game as gg
 
     gg.lib()
     seeds = tuple(range(args.target_seeds))
-    if args.only in ("bf16", "batched", "target", "paper", "trig"):
+    if args.only in ("bf16", "batched", "target", "paper", "trig", "long_target"):
         if args.only == "trig":
             log("trig expansion on the scale patterns: building inputs")
             res = form_trig(gg, datagen.scale())
@@ -718,6 +781,9 @@ def main():
             log("time to target: building inputs")
             res = form_time_to_target(gg, precision_problem(), args.target_generations,
                                       seeds=seeds)
+        elif args.only == "long_target":
+            log("long-horizon time to target: building inputs")
+            res = form_long_horizon(gg, precision_problem(), args.long_generations)
         else:
             res = form_paper_shaped(gg)
         print(json.dumps({"only": args.only, "result": res}), flush=True)
