@@ -12,14 +12,27 @@ namespace game {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// Squared residual (MSE, RMSE) or its thresholded form (TMSE, Eq. 10):
-// mode 2 keeps it when |r| > R, mode 3 when r^2 > R.
+// s plus the squared residual v (MSE, RMSE: one fused multiply-add) or its
+// thresholded form (TMSE, Eq. 10: mode 2 keeps it when |v| > R, mode 3 when
+// v^2 > R; square and sum rounded separately).  Every rounding is spelled
+// out, so each instance of the body (single-run and batched) sums the same
+// bits whatever the compiler would contract.
 template <int MODE>
-__device__ __forceinline__ float error_term(float v, float R) {
-  const float e = v * v;
-  if constexpr (MODE == 2) return fabsf(v) > R ? e : 0.f;
-  if constexpr (MODE == 3) return e > R ? e : 0.f;
-  return e;
+__device__ __forceinline__ float add_error_term(float s, float v, float R) {
+  if constexpr (MODE == 2 || MODE == 3) {
+    const float e = __fmul_rn(v, v);
+    const bool keep = MODE == 2 ? fabsf(v) > R : e > R;
+    return __fadd_rn(s, keep ? e : 0.f);
+  }
+  return __builtin_fmaf(v, v, s);
+}
+
+// A recurrence chain that yields zero at every degree: for rows past the
+// data, so that their accumulators end at exactly zero.
+template <class R>
+__device__ __forceinline__ void zero_chain(R& r, bool keep) {
+  r.cur = keep ? r.cur : 0.f;
+  if constexpr (requires { r.prev; }) r.prev = keep ? r.prev : 0.f;
 }
 
 // Wave-uniform copies (readfirstlane) of launch parameters.
@@ -178,6 +191,12 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
 
   for (int tile = tile_begin; tile < tile_end; ++tile) {
     const int64_t row0 = (int64_t)tile * kTileRows + wave * 64;
+    // Rows past the data take a zero A operand in every K-step (bias step
+    // included), so their residuals are exactly zero and the epilogue needs
+    // no row mask.
+    bool row_ok[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) row_ok[rb] = row0 + rb * 32 + m < NP;
     // Minus the targets of this lane's rows (0 past the data); they join
     // with the bias in a last K-step, so the load's latency hides behind the
     // K loop.
@@ -222,6 +241,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
           } else {
             rc[rb].seed(x[rb], h);
           }
+          zero_chain(rc[rb], row_ok[rb]);
         }
         const float* wl = wbuf + m * WS + (2 * (q - q_begin) + h) * Dv;
         // One K-step per degree: two MFMA columns x two row blocks, then the
@@ -251,19 +271,19 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
 
     // Bias and target K-step: lane half 0 multiplies 1 by a0 of its column,
     // half 1 multiplies -t of its row by 1, so the accumulators end at
-    // Out - t.
+    // Out - t (0 for rows past the data).
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
-      const float ab = h ? nt[rb] : 1.f;
+      const float ab = h ? nt[rb] : (row_ok[rb] ? 1.f : 0.f);
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb)
         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ab, h ? 1.f : w0[cb], acc[rb][cb], 0, 0, 0);
     }
 
     // Epilogue: residual Out - t, squared (or thresholded), summed over the
-    // lane's 32 rows.  Accumulator register i of row block rb holds row
-    // rb*32 + 8*(i/4) + 4*h + i%4 of the wave's 64 rows.
-    const bool full = row0 + 64 <= NP;
+    // lane's 32 rows (register order; accumulator register i of row block rb
+    // holds row rb*32 + 8*(i/4) + 4*h + i%4 of the wave's 64 rows).  Rows
+    // past the data add exactly zero.
     float s[2] = {0.f, 0.f};
     auto epilogue = [&](auto mode_c) {
       constexpr int mode = decltype(mode_c)::value;
@@ -271,16 +291,8 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
       for (int rb = 0; rb < 2; ++rb) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-          const int rl = rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-          float e0 = error_term<mode>(acc[rb][0][i], a.R);
-          float e1 = error_term<mode>(acc[rb][1][i], a.R);
-          if (!full) {
-            const bool ok = row0 + rl < NP;
-            e0 = ok ? e0 : 0.f;
-            e1 = ok ? e1 : 0.f;
-          }
-          s[0] += e0;
-          s[1] += e1;
+          s[0] = add_error_term<mode>(s[0], acc[rb][0][i], a.R);
+          s[1] = add_error_term<mode>(s[1], acc[rb][1][i], a.R);
         }
       }
     };
