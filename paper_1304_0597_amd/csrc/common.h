@@ -87,7 +87,7 @@ struct FitArgs {
   int32_t pairs_per_chunk;
   int32_t n_chunks;
   int32_t n_ctiles;
-  int32_t ld_partial;       // n_ctiles * 64
+  int32_t ld_partial;       // n_ctiles * tile_cols
   int32_t n_splits;
   int32_t tiles_per_split;
   int32_t n_tiles;
@@ -95,16 +95,19 @@ struct FitArgs {
   int32_t error_fn;
   float R;
   int32_t degree;           // d
-  int32_t basis;            // expansion family, read by the run-time-family body only
+  int32_t basis;            // expansion family (the kernels take it as a template parameter)
   const float* cs;          // trig only: [NP x N] pairs (cos x, sin x) of X, or null
+  int32_t tile_cols;        // chromosomes per FP32 tile: 64, or 128 (genes in one chunk)
 };
 
 // Fitness-kernel variant of the trigonometric expansion that reads the
 // stored (cos x, sin x) table FitArgs::cs.
 constexpr int kTrigTable = 4;
 
-// Grid/chunk planning shared by every fitness launch.
-void plan_fitness(FitArgs& a, int degree, int basis);
+// Grid/chunk planning shared by every float32 fitness launch.  wide allows
+// 128-chromosome tiles (single runs); the batched kernel's items are 64
+// chromosomes wide.
+void plan_fitness(FitArgs& a, int degree, int basis, bool wide);
 size_t fitness_lds_bytes(const FitArgs& a, int degree);
 
 hipError_t launch_fitness_f32(const FitArgs& a, int basis, int degree, hipStream_t s);

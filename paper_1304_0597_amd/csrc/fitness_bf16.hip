@@ -538,6 +538,7 @@ void plan_fitness_bf16(FitArgs& a, int degree, int basis) {
   a.pairs_per_chunk = gpc;
   a.n_chunks = (a.Q + gpc - 1) / gpc;
   a.n_ctiles = (a.n_chrom + 127) / 128;
+  a.tile_cols = 128;
   a.ld_partial = a.n_ctiles * 128;
   a.n_tiles = (int32_t)((a.NP + kTileRows - 1) / kTileRows);
   const int target = 512;

@@ -30,15 +30,22 @@
 //    the lane's feature.  For the run's own data set they come from a table
 //    computed once per data set (FitArgs::cs); otherwise sincosf in every
 //    chromosome tile.
-//  * Grid: (pattern split) x (64-chromosome tile); consecutive blocks of one
+//  * Wave tile 64 patterns x 32*CB chromosomes: each generated A value feeds
+//    CB MFMAs per row block.  When a run's genes fit one LDS chunk and its
+//    population exceeds 64, a workgroup takes 128 chromosomes (CB = 4) with
+//    eight waves, waves 0-3 on the even pattern tiles of its split and 4-7
+//    on the odd ones (two waves per SIMD, one gene copy per CU); otherwise
+//    64 chromosomes (CB = 2) with four waves and two workgroups per CU.  The
+//    wider tile halves the recurrence and feature-load work per MFMA.
+//  * Grid: (pattern split) x (chromosome tile); consecutive blocks of one
 //    split are mapped onto one XCD so its L2 serves the split's rows to all
 //    chromosome tiles.
 #include "fitness_f32_body.h"
 
 namespace game {
 
-template <int BASIS, int D>
-__global__ __launch_bounds__(kFitThreads, 2) void fitness_f32_kernel(FitArgs a) {
+template <int BASIS, int D, int CB>
+__global__ __launch_bounds__(64 * fit_waves(CB), 8 / fit_waves(CB)) void fitness_f32_kernel(FitArgs a) {
   extern __shared__ float lds[];
   if (a.stop) {
     const int32_t stopped = *a.stop;
@@ -52,20 +59,30 @@ __global__ __launch_bounds__(kFitThreads, 2) void fitness_f32_kernel(FitArgs a) 
   const int L = a.xcd_remap ? (b & 7) * (total >> 3) + (b >> 3) : b;
   const int split = L / a.n_ctiles;
   const int ctile = L - split * a.n_ctiles;
-  fitness_f32_block<BASIS, D>(a, genes, split, ctile, lds);
+  fitness_f32_block<BASIS, D, CB>(a, genes, split, ctile, lds);
+}
+
+template <int BASIS, int D, int CB>
+static hipError_t launch_cb(const FitArgs& a, hipStream_t s) {
+  const size_t lds = fitness_lds_bytes(a, D);
+  const int grid = a.n_ctiles * a.n_splits;
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)fitness_f32_kernel<BASIS, D, CB>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((fitness_f32_kernel<BASIS, D, CB>), dim3(grid), dim3(64 * fit_waves(CB)), lds,
+                     s, a);
+  return hipGetLastError();
 }
 
 template <int BASIS, int D>
 static hipError_t launch_one(const FitArgs& a, hipStream_t s) {
-  const size_t lds = fitness_lds_bytes(a, D);
-  const int grid = a.n_ctiles * a.n_splits;
-  if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute((const void*)fitness_f32_kernel<BASIS, D>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  if (a.tile_cols == 128) {
+    if (a.n_chunks != 1) return hipErrorInvalidValue;  // the wide body needs the whole K in LDS
+    return launch_cb<BASIS, D, 4>(a, s);
   }
-  hipLaunchKernelGGL((fitness_f32_kernel<BASIS, D>), dim3(grid), dim3(kFitThreads), lds, s, a);
-  return hipGetLastError();
+  return launch_cb<BASIS, D, 2>(a, s);
 }
 
 template <int BASIS>
@@ -91,24 +108,28 @@ hipError_t launch_fitness_f32(const FitArgs& a, int basis, int degree, hipStream
 }
 
 size_t fitness_lds_bytes(const FitArgs& a, int degree) {
-  const size_t w = (size_t)(a.n_chunks > 1 ? 2 : 1) * kTileCols *
+  const int cols = a.tile_cols == 128 ? 128 : kTileCols;
+  const size_t w = (size_t)(a.n_chunks > 1 ? 2 : 1) * cols *
                    (2 * a.pairs_per_chunk * degree + 1) * sizeof(float);
-  const size_t red = 4 * 64 * sizeof(double);
+  const size_t red = (size_t)fit_waves(cols / 32) * cols * sizeof(double);
   return w > red ? w : red;
 }
 
-void plan_fitness(FitArgs& a, int degree, int basis) {
+void plan_fitness(FitArgs& a, int degree, int basis, bool wide) {
   a.U = (basis == 3 ? 2 : 1) * a.N;
   a.Q = (a.U + 1) / 2;
   int ppc = a.Q * degree <= kMaxChunkSteps ? a.Q : kChunkSteps / degree;
   if (ppc < 1) ppc = 1;
   a.pairs_per_chunk = ppc;
   a.n_chunks = (a.Q + ppc - 1) / ppc;
-  a.n_ctiles = (a.n_chrom + kTileCols - 1) / kTileCols;
-  a.ld_partial = a.n_ctiles * kTileCols;
+  a.tile_cols = wide && a.n_chunks == 1 && a.n_chrom > kTileCols ? 128 : kTileCols;
+  a.n_ctiles = (a.n_chrom + a.tile_cols - 1) / a.tile_cols;
+  a.ld_partial = a.n_ctiles * a.tile_cols;
   a.n_tiles = (int32_t)((a.NP + kTileRows - 1) / kTileRows);
-  // Aim at two resident workgroups per CU on 256 CUs in one wave of blocks.
-  const int target = 512;
+  // Aim at all resident workgroups on 256 CUs in one wave of blocks: one
+  // eight-wave workgroup per CU for 128-chromosome tiles, two four-wave ones
+  // for 64-chromosome tiles.
+  const int target = a.tile_cols == 128 ? 256 : 512;
   int splits = (target + a.n_ctiles - 1) / a.n_ctiles;
   if (splits > max_splits(a.ld_partial)) splits = max_splits(a.ld_partial);
   if (splits > a.n_tiles) splits = a.n_tiles;

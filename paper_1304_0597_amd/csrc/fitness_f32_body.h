@@ -55,13 +55,19 @@ __device__ __forceinline__ T* uniform(T* p) {
 typedef const float __attribute__((address_space(1)))* gptr_f32;
 __device__ __forceinline__ gptr_f32 global_f32(const float* p) { return (gptr_f32)p; }
 
-// Tile range [split's tiles] x chromosome tile ctile of the launch described
-// by a_in; writes a.partial[split * ld_partial + chromosome].  genes: the
-// chromosomes being scored; lds: the workgroup's dynamic LDS.  D is the
-// degree.  BASIS is the expansion family (kTrigTable: the trigonometric one
-// seeded from the stored (cos x, sin x) table a_in.cs instead of sincosf in
-// every tile).
-template <int BASIS, int D>
+// Waves per workgroup of the body with CB 32-column blocks per wave: four
+// for 64-chromosome tiles, eight for 128-chromosome tiles (waves 0-3 take
+// the even row tiles of the split and 4-7 the odd ones, two per SIMD).
+__host__ __device__ constexpr int fit_waves(int cb) { return cb == 4 ? 8 : 4; }
+
+// Tile range [split's tiles] x chromosome tile ctile (32*CB chromosomes) of
+// the launch described by a_in; writes a.partial[split * ld_partial +
+// chromosome].  genes: the chromosomes being scored; lds: the workgroup's
+// dynamic LDS.  D is the degree.  BASIS is the expansion family (kTrigTable:
+// the trigonometric one seeded from the stored (cos x, sin x) table a_in.cs
+// instead of sincosf in every tile).  CB = 4 needs the whole K in one chunk
+// (n_chunks == 1): its two wave groups walk different numbers of tiles.
+template <int BASIS, int D, int CB = 2>
 __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const float* __restrict__ genes,
                                                   int split, int ctile, float* lds) {
   // The parameters the body uses, read once into scalar registers (so that
@@ -77,7 +83,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   a.U = uniform(a_in.U);
   a.Q = uniform(a_in.Q);
   a.pairs_per_chunk = uniform(a_in.pairs_per_chunk);
-  a.n_chunks = uniform(a_in.n_chunks);
+  a.n_chunks = CB == 4 ? 1 : uniform(a_in.n_chunks);
   a.ld_partial = uniform(a_in.ld_partial);
   a.tiles_per_split = uniform(a_in.tiles_per_split);
   a.n_tiles = uniform(a_in.n_tiles);
@@ -94,23 +100,29 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   split = uniform(split);
   ctile = uniform(ctile);
   lds = uniform(lds);
+  static_assert(CB == 2 || CB == 4, "64- or 128-chromosome tiles");
+  constexpr int NW = fit_waves(CB);   // waves per workgroup
+  constexpr int TS = NW / 4;          // row tiles in flight (tile stride)
+  constexpr int kCols = 32 * CB;      // chromosomes per tile
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  const int wq = wave & 3;            // 64-row slice of a tile
+  const int wg = wave >> 2;           // tile stream
   const int m = lane & 31;
   const int h = lane >> 5;
-  const int c0 = ctile * kTileCols;
+  const int c0 = ctile * kCols;
 
   const int ppc = a.pairs_per_chunk;
   const int SC = ppc * Dv;         // K-steps per chunk
   const int WS = 2 * SC + 1;       // LDS row stride in floats (odd)
-  const int BUF = kTileCols * WS;  // floats per gene buffer
+  const int BUF = kCols * WS;      // floats per gene buffer
   const int nk = (2 * SC + 63) >> 6;  // 64-gene pieces of a row
   const int K = a.K;
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
 
-  float w0[2];
+  float w0[CB];
 #pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
+  for (int cb = 0; cb < CB; ++cb) {
     const int n = c0 + cb * 32 + m;
     w0[cb] = n < a.n_chrom ? global_f32(genes)[(int64_t)n * K] : 0.f;
   }
@@ -127,7 +139,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
     const int valid = min(2 * SC, rem * Dv);
     float* dst0 = lds + buf * BUF;
     const float* src0 = genes + 1 + u0 * Dv + lane;
-    for (int i = wave_u; i < kTileCols * nk; i += kFitThreads / 64) {
+    for (int i = wave_u; i < kCols * nk; i += NW) {
       const int c = i / nk;
       const int k = i - c * nk;
       const int n = min(c0 + c, a.n_chrom - 1);
@@ -137,7 +149,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
             (__attribute__((address_space(3))) void*)(dst0 + c * WS + k * 64), 4, 0, 0);
     }
     if ((rem & 1) && rem < 2 * ppc) {
-      for (int idx = threadIdx.x; idx < kTileCols * Dv; idx += kFitThreads) {
+      for (int idx = threadIdx.x; idx < kCols * Dv; idx += 64 * NW) {
         const int c = idx / Dv;
         dst0[c * WS + rem * Dv + (idx - c * Dv)] = 0.f;
       }
@@ -150,7 +162,9 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
     __syncthreads();
   }
 
-  double acc64[2] = {0.0, 0.0};
+  double acc64[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) acc64[cb] = 0.0;
   const int64_t NP = a.NP;
   const int N = a.N;
   const int tile_begin = split * a.tiles_per_split;
@@ -183,14 +197,14 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   };
 
   float xn[2] = {0.f, 0.f}, sn[2] = {0.f, 0.f};
-  if (tile_begin < tile_end) load_x((int64_t)tile_begin * kTileRows + wave * 64, 0, xn, sn);
+  if (tile_begin + wg < tile_end) load_x((int64_t)(tile_begin + wg) * kTileRows + wq * 64, 0, xn, sn);
   // Chunked genes: stage index st runs over (tile, chunk) in loop order and
   // uses buffer st & 1.
   int st = 0;
   if (a.n_chunks > 1 && tile_begin < tile_end) stage_issue(0, 0);
 
-  for (int tile = tile_begin; tile < tile_end; ++tile) {
-    const int64_t row0 = (int64_t)tile * kTileRows + wave * 64;
+  for (int tile = tile_begin + wg; tile < tile_end; tile += TS) {
+    const int64_t row0 = (int64_t)tile * kTileRows + wq * 64;
     // Rows past the data take a zero A operand in every K-step (bias step
     // included), so their residuals are exactly zero and the epilogue needs
     // no row mask.
@@ -208,11 +222,11 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
     }
     // Accumulators start at zero (an inline constant, nothing to keep live
     // across tiles).
-    f32x16 acc[2][2];
-    acc[0][0] = f32x16{};
-    acc[0][1] = f32x16{};
-    acc[1][0] = f32x16{};
-    acc[1][1] = f32x16{};
+    f32x16 acc[2][CB];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = f32x16{};
 
     for (int chunk = 0; chunk < a.n_chunks; ++chunk) {
       const float* wbuf = lds;
@@ -222,7 +236,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
         __syncthreads();
         if (chunk + 1 < a.n_chunks) stage_issue(chunk + 1, (st + 1) & 1);
-        else if (tile + 1 < tile_end) stage_issue(0, (st + 1) & 1);
+        else if (tile + TS < tile_end) stage_issue(0, (st + 1) & 1);
         wbuf = lds + (st & 1) * BUF;
         ++st;
       }
@@ -232,7 +246,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
         float x[2] = {xn[0], xn[1]}, sx[2] = {sn[0], sn[1]};
         // prefetch the next pair, or the first pair of the next tile
         if (q + 1 < a.Q) load_x(row0, q + 1, xn, sn);
-        else if (tile + 1 < tile_end) load_x(row0 + kTileRows, 0, xn, sn);
+        else if (tile + TS < tile_end) load_x(row0 + TS * kTileRows, 0, xn, sn);
         Recur<FAM> rc[2];
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
@@ -244,18 +258,18 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
           zero_chain(rc[rb], row_ok[rb]);
         }
         const float* wl = wbuf + m * WS + (2 * (q - q_begin) + h) * Dv;
-        // One K-step per degree: two MFMA columns x two row blocks, then the
+        // One K-step per degree: CB MFMA columns x two row blocks, then the
         // recurrence moves every lane's A value to the next degree.
-        auto mfma4 = [&](float b0, float b1) {
-#pragma unroll
-          for (int rb = 0; rb < 2; ++rb) {
-            acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(rc[rb].cur, b0, acc[rb][0], 0, 0, 0);
-            acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(rc[rb].cur, b1, acc[rb][1], 0, 0, 0);
-          }
-        };
         auto kstep = [&](auto jc) {
           constexpr int j = decltype(jc)::value;
-          mfma4(wl[j], wl[32 * WS + j]);
+          float b[CB];
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) b[cb] = wl[cb * 32 * WS + j];
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+              acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(rc[rb].cur, b[cb], acc[rb][cb], 0, 0, 0);
           if constexpr (j + 1 < D) {
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb) {
@@ -276,7 +290,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
     for (int rb = 0; rb < 2; ++rb) {
       const float ab = h ? nt[rb] : (row_ok[rb] ? 1.f : 0.f);
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+      for (int cb = 0; cb < CB; ++cb)
         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ab, h ? 1.f : w0[cb], acc[rb][cb], 0, 0, 0);
     }
 
@@ -284,39 +298,41 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
     // lane's 32 rows (register order; accumulator register i of row block rb
     // holds row rb*32 + 8*(i/4) + 4*h + i%4 of the wave's 64 rows).  Rows
     // past the data add exactly zero.
-    float s[2] = {0.f, 0.f};
+    float s[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) s[cb] = 0.f;
     auto epilogue = [&](auto mode_c) {
       constexpr int mode = decltype(mode_c)::value;
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
+      for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          s[0] = add_error_term<mode>(s[0], acc[rb][0][i], a.R);
-          s[1] = add_error_term<mode>(s[1], acc[rb][1][i], a.R);
-        }
-      }
+        for (int i = 0; i < 16; ++i)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) s[cb] = add_error_term<mode>(s[cb], acc[rb][cb][i], a.R);
     };
     if (a.error_fn == 2) epilogue(std::integral_constant<int, 2>{});
     else if (a.error_fn == 3) epilogue(std::integral_constant<int, 3>{});
     else epilogue(std::integral_constant<int, 0>{});
-    acc64[0] += (double)s[0];
-    acc64[1] += (double)s[1];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) acc64[cb] += (double)s[cb];
   }
 
   // Combine the two lane halves (same chromosome, different rows), then the
-  // four waves, in a fixed order.
+  // waves, in a fixed order.
 #pragma unroll
-  for (int cb = 0; cb < 2; ++cb) acc64[cb] += __shfl_xor(acc64[cb], 32);
+  for (int cb = 0; cb < CB; ++cb) acc64[cb] += __shfl_xor(acc64[cb], 32);
   __syncthreads();
   double* red = reinterpret_cast<double*>(lds);
   if (h == 0) {
-    red[wave * 64 + m] = acc64[0];
-    red[wave * 64 + 32 + m] = acc64[1];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) red[wave * kCols + cb * 32 + m] = acc64[cb];
   }
   __syncthreads();
-  if (threadIdx.x < 64) {
+  if (threadIdx.x < kCols) {
     const int c = threadIdx.x;
-    const double v = ((red[c] + red[64 + c]) + red[128 + c]) + red[192 + c];
+    double v = red[c];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += red[w * kCols + c];
     a.partial[(int64_t)split * a.ld_partial + c0 + c] = v;
   }
 }

@@ -202,7 +202,7 @@ FitArgs fit_args(const game_ctx* h, const float* X, const float* t, int64_t NP, 
   a.basis = h->cfg.basis;
   a.cs = X == h->X && NP == h->NP ? h->cs : nullptr;
   if (h->cfg.precision == GAME_BF16) plan_fitness_bf16(a, h->cfg.degree, h->cfg.basis);
-  else plan_fitness(a, h->cfg.degree, h->cfg.basis);
+  else plan_fitness(a, h->cfg.degree, h->cfg.basis, true);
   return a;
 }
 
@@ -1537,7 +1537,7 @@ int game_batch_create(const game_run_desc* runs, int32_t n_runs, void* ws, size_
     fa.NP = runs[i].n_patterns;
     fa.N = runs[i].n_features;
     fa.n_chrom = c.population;
-    plan_fitness(fa, c.degree, c.basis);
+    plan_fitness(fa, c.degree, c.basis, false);
     lds = std::max(lds, fitness_lds_bytes(fa, c.degree));
     BatchRun r{};
     r.X = runs[i].X_dev;
