@@ -123,7 +123,9 @@ def cpu_serial(prob, seconds=5.0):
 def time_median(fn, stream, reps=25, warmup=3):
     """Median duration (s) of `reps` calls of fn(), each bracketed by its own
     pair of HIP events on `stream` (the stream the library queues on), after
-    `warmup` untimed calls."""
+    `warmup` untimed calls.  After an idle moment the GPU clock needs about
+    20 ms of sustained load to come back up (a fitness launch then runs up
+    to 20 % slower), so the fitness timings warm up for longer than that."""
     import torch
     for _ in range(warmup):
         fn()
@@ -139,10 +141,12 @@ def time_median(fn, stream, reps=25, warmup=3):
 
 def time_fitness(gg, game, genes, n, reps, stream):
     """Median duration (s) of one fitness launch (plus its few-microsecond
-    finish kernel) on the library's stream, HIP events around each launch."""
+    finish kernel) on the library's stream, HIP events around each launch,
+    after 30 untimed launches."""
     import torch
     f32 = torch.empty(n, dtype=torch.float32, device=genes.device)
-    return time_median(lambda: gg.game_fitness(game.h, genes, n, f32), stream, reps=max(20, reps))
+    return time_median(lambda: gg.game_fitness(game.h, genes, n, f32), stream, reps=max(20, reps),
+                       warmup=30)
 
 
 def time_steps(game, steps, warmup):
@@ -198,7 +202,9 @@ def form_bf16(gg, prob, steps, warmup):
             "ms_per_step": elapsed * 1e3 / steps, "dtype": "bf16",
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK_TFLOPS,
-                         "traffic": profiled_traffic("fitness_bf16_precision.md"), "kernel_ms": t_kernel * 1e3, "flops_per_launch": flops},
+                         "traffic": profiled_traffic("fitness_bf16_precision.md"), "kernel_ms": t_kernel * 1e3,
+                         "kernel_timing": f"median of {max(20, max(10, steps))} launches",
+                         "flops_per_launch": flops},
             "error_vs_float64": {"max_rel": float(rel.max()), "median_rel": float(np.median(rel)),
                                  "sample": f"{idx.numel()} chromosomes of the population, "
                                            "float64 re-score on the GPU"}}
@@ -633,7 +639,7 @@ def form_batched(gg, steps, warmup, decomposition=None, autotune=False):
     elapsed = time.perf_counter() - t0
     n_items, _, grid = batch.items()
     # the evaluation launch of that decomposition alone, median of 25
-    t_kernel = time_median(batch.evaluate, torch.cuda.current_stream(), reps=25)
+    t_kernel = time_median(batch.evaluate, torch.cuda.current_stream(), reps=25, warmup=5)
     batch.close()
     achieved = flops / t_kernel / 1e12
     return {"workload": "batched: 256 independent runs, patterns 1e3-2e5 log-uniform, features "

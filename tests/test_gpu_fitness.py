@@ -61,6 +61,9 @@ SHAPES = [
     (513, 64, 2, 100), (300, 33, 10, 70), (1100, 300, 1, 66),
     # few chromosomes over many patterns: hundreds of pattern splits
     (300001, 4, 2, 10),
+    # 128-chromosome tiles over splits of 4 pattern tiles and a last split
+    # of 3 (the two wave groups of a workgroup walk unequal tile counts)
+    (100000, 5, 3, 200),
     # K-chunks through the two gene buffers over several tiles per split,
     # odd sub-feature count (zeroed half pair in the last chunk)
     (8000, 33, 10, 1100),
