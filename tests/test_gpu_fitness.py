@@ -139,6 +139,24 @@ def test_nan_input_gives_infinite_error(gg):
     assert np.all(np.isinf(f32)) and np.all(np.isinf(f64))
 
 
+@pytest.mark.parametrize("P", [10, 200], ids=["64-chromosome-tiles", "128-chromosome-tiles"])
+def test_non_finite_genes_give_infinite_error(gg, P):
+    """Rows past the data take a zero A operand; a chromosome with a NaN or
+    infinite gene must still end at +inf (its valid rows are non-finite),
+    and its neighbours must keep their oracle values, over a ragged last
+    pattern tile (777 rows)."""
+    X, t, W = problem(777, 5, 3, P, 0, seed=11)
+    bad = [1, P // 2, P - 1]
+    W[bad[0], 4] = np.nan
+    W[bad[1], 7] = -np.inf
+    W[bad[2], 0] = np.inf           # the bias gene
+    f32, f64 = gpu_fitness(gg, 0, 3, X, t, W)
+    assert np.all(np.isposinf(f32[bad])) and np.all(np.isposinf(f64[bad]))
+    good = np.setdiff1d(np.arange(P), bad)
+    ref = og.fitness(X, t, W[good], 0, 3)
+    assert within(f64[good], ref, t).all()
+
+
 def test_deterministic_bitwise(gg):
     X, t, W = problem(4000, 11, 6, 200, 1, seed=9)
     a = gpu_fitness(gg, 1, 6, X, t, W)[1]
