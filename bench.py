@@ -603,6 +603,48 @@ def form_trig(gg, prob, reps=25):
                          "flops_per_launch": flops}}
 
 
+def form_degree_sweep(gg, degrees=(1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16), reps=25):
+    """The fused fitness kernels across degrees on the precision problem's
+    shape (1,000,000 patterns x 32 features, Chebyshev, population 4,096,
+    K - 1 = 32 d expansion terms): FP32 and BF16 kernel time (median of
+    `reps` HIP-event-timed launches after 30 untimed ones) and fraction of
+    each precision's MFMA peak.  Shows the tile choices the plans make: FP32
+    128-chromosome tiles while the genes fit one LDS chunk (d <= 8 here),
+    64-chromosome tiles through two gene buffers above; BF16 eight waves
+    per workgroup where a lane half's group holds at most 4 sub-features,
+    four waves otherwise."""
+    import torch
+    from paper_1304_0597_amd import datagen
+    dev = torch.device("cuda:0")
+    NP, N, P = 1_000_000, 32, 4096
+    rng = np.random.default_rng(11)
+    X = torch.from_numpy(rng.uniform(-1, 1, (NP, N)).astype(np.float32)).to(dev)
+    t = torch.from_numpy(rng.normal(0, 1, NP).astype(np.float32)).to(dev)
+    rows = []
+    for d in degrees:
+        row = {"degree": d}
+        for name, precision, peak in (("fp32", gg.GAME_FP32, FP32_MFMA_PEAK_TFLOPS),
+                                      ("bf16", gg.GAME_BF16, BF16_MFMA_PEAK_TFLOPS)):
+            cfg = gg.config(basis=datagen.CHEBYSHEV, degree=d, population=P, precision=precision,
+                            seed=d, max_generations=1 << 30, target=-1.0)
+            game = gg.Game(cfg, X, t)
+            game.init_population()
+            pop, _ = game.population()
+            t_kernel = time_fitness(gg, game, pop, P, reps, torch.cuda.current_stream())
+            game.close()
+            K = gg.game_num_genes(cfg, N)
+            tf = 2.0 * (K - 1) * P * NP / t_kernel / 1e12
+            row["genes"] = K
+            row[name] = {"kernel_ms": round(t_kernel * 1e3, 4), "tflops": round(tf, 1),
+                         "frac": round(tf / peak, 4)}
+        rows.append(row)
+        log(f"degree sweep: d = {d}: FP32 {row['fp32']['frac']:.3f}, BF16 {row['bf16']['frac']:.3f}")
+    return {"workload": "1,000,000 patterns x 32 features (uniform), Chebyshev degree d, "
+                        "population 4,096; fused fitness kernel per precision",
+            "kernel_timing": f"median of {reps} launches after 30 untimed ones",
+            "rows": rows}
+
+
 def form_batched(gg, steps, warmup, decomposition=None, autotune=False):
     """Batched form: the 256 runs of the batched workload (sizes drawn from
     seed 3) advanced together, FP32.  The work decomposition is the committed
@@ -734,7 +776,7 @@ def main():
     ap.add_argument("--long-generations", type=int, default=5000,
                     help="--only long_target: generations of the plain FP32 reference run")
     ap.add_argument("--only", choices=["scale", "bf16", "batched", "target", "paper", "trig",
-                                       "long_target"],
+                                       "long_target", "degrees"],
                     help="run one workload alone and print its result (for profiling)")
     ap.add_argument("--batch-decomp", type=str, default=None,
                     help="batched form: a uniform 'tiles,grid' instead of the committed table")
@@ -772,7 +814,7 @@ def main():
 
     gg.lib()
     seeds = tuple(range(args.target_seeds))
-    if args.only in ("bf16", "batched", "target", "paper", "trig", "long_target"):
+    if args.only in ("bf16", "batched", "target", "paper", "trig", "long_target", "degrees"):
         if args.only == "trig":
             log("trig expansion on the scale patterns: building inputs")
             res = form_trig(gg, datagen.scale())
@@ -787,6 +829,9 @@ def main():
             log("time to target: building inputs")
             res = form_time_to_target(gg, precision_problem(), args.target_generations,
                                       seeds=seeds)
+        elif args.only == "degrees":
+            log("degree sweep: FP32 and BF16 fitness kernels on 1,000,000 x 32")
+            res = form_degree_sweep(gg)
         elif args.only == "long_target":
             log("long-horizon time to target: building inputs")
             res = form_long_horizon(gg, precision_problem(), args.long_generations)

@@ -526,13 +526,17 @@ static bool use_xl(const FitArgs& a, int degree) {
 }
 
 // Plan: Q = number of groups of 2G sub-features; pairs_per_chunk = groups
-// staged in LDS at once (at most 16 K-steps); 128-chromosome tiles.
+// staged in LDS at once: all of them when their BF16 genes fit a CU's LDS
+// (staged once per workgroup; the feature copy buffers then come only if
+// they fit beside them, see use_xl), otherwise 16 K-steps' worth per chunk,
+// restaged for every pattern tile; 128-chromosome tiles.
 void plan_fitness_bf16(FitArgs& a, int degree, int basis) {
+  constexpr size_t kLdsPerCu = 160 * 1024;
   const int G = group_size(degree);
   const int KS = G * degree / 8;
   a.U = (basis == 3 ? 2 : 1) * a.N;
   a.Q = (a.U + 2 * G - 1) / (2 * G);
-  int gpc = 16 / KS;
+  int gpc = (size_t)128 * bf16_row_bytes(a.Q * KS) <= kLdsPerCu ? a.Q : 16 / KS;
   if (gpc < 1) gpc = 1;
   if (gpc > a.Q) gpc = a.Q;
   a.pairs_per_chunk = gpc;
