@@ -51,8 +51,11 @@ constexpr int kFitThreads = 256;
 // Largest K kept in LDS at once, in MFMA K-steps per lane half: a
 // chromosome tile whose genes fit is staged once; otherwise its genes pass
 // through two LDS buffers in chunks of at most kChunkSteps K-steps, the next
-// chunk's copy in flight while the current one is used.
+// chunk's copy in flight while the current one is used.  kMaxChunkSteps for
+// 64-chromosome tiles (two workgroups share a CU's LDS), kMaxWideSteps for
+// 128-chromosome ones (128 rows x 319 floats = 159.5 KB of one CU).
 constexpr int kMaxChunkSteps = 128;
+constexpr int kMaxWideSteps = 159;
 constexpr int kChunkSteps = 64;
 
 // Device-side state of a run.  Only the rank kernel writes gen/stop/best.

@@ -31,12 +31,13 @@
 //    computed once per data set (FitArgs::cs); otherwise sincosf in every
 //    chromosome tile.
 //  * Wave tile 64 patterns x 32*CB chromosomes: each generated A value feeds
-//    CB MFMAs per row block.  When a run's genes fit one LDS chunk and its
-//    population exceeds 64, a workgroup takes 128 chromosomes (CB = 4) with
-//    eight waves, waves 0-3 on the even pattern tiles of its split and 4-7
-//    on the odd ones (two waves per SIMD, one gene copy per CU); otherwise
-//    64 chromosomes (CB = 2) with four waves and two workgroups per CU.  The
-//    wider tile halves the recurrence and feature-load work per MFMA.
+//    CB MFMAs per row block.  For a single run whose population exceeds 64
+//    a workgroup takes 128 chromosomes (CB = 4) with eight waves, waves 0-3
+//    on the even pattern tiles of its split and 4-7 on the odd ones (two
+//    waves per SIMD, one gene copy per CU, up to 159 K-steps of genes before
+//    they are chunked); otherwise 64 chromosomes (CB = 2) with four waves
+//    and two workgroups per CU (up to 128 K-steps).  The wider tile halves
+//    the recurrence and feature-load work per MFMA.
 //  * Grid: (pattern split) x (chromosome tile); consecutive blocks of one
 //    split are mapped onto one XCD so its L2 serves the split's rows to all
 //    chromosome tiles.
@@ -78,10 +79,7 @@ static hipError_t launch_cb(const FitArgs& a, hipStream_t s) {
 
 template <int BASIS, int D>
 static hipError_t launch_one(const FitArgs& a, hipStream_t s) {
-  if (a.tile_cols == 128) {
-    if (a.n_chunks != 1) return hipErrorInvalidValue;  // the wide body needs the whole K in LDS
-    return launch_cb<BASIS, D, 4>(a, s);
-  }
+  if (a.tile_cols == 128) return launch_cb<BASIS, D, 4>(a, s);
   return launch_cb<BASIS, D, 2>(a, s);
 }
 
@@ -118,11 +116,15 @@ size_t fitness_lds_bytes(const FitArgs& a, int degree) {
 void plan_fitness(FitArgs& a, int degree, int basis, bool wide) {
   a.U = (basis == 3 ? 2 : 1) * a.N;
   a.Q = (a.U + 1) / 2;
-  int ppc = a.Q * degree <= kMaxChunkSteps ? a.Q : kChunkSteps / degree;
+  a.tile_cols = wide && a.n_chrom > kTileCols ? 128 : kTileCols;
+  // K-steps (per lane half) of genes that stay in LDS for the whole launch:
+  // two 64-chromosome workgroups share a CU, a 128-chromosome one has it to
+  // itself; beyond that the genes pass through two buffers in chunks.
+  const int max_steps = a.tile_cols == 128 ? kMaxWideSteps : kMaxChunkSteps;
+  int ppc = a.Q * degree <= max_steps ? a.Q : kChunkSteps / degree;
   if (ppc < 1) ppc = 1;
   a.pairs_per_chunk = ppc;
   a.n_chunks = (a.Q + ppc - 1) / ppc;
-  a.tile_cols = wide && a.n_chunks == 1 && a.n_chrom > kTileCols ? 128 : kTileCols;
   a.n_ctiles = (a.n_chrom + a.tile_cols - 1) / a.tile_cols;
   a.ld_partial = a.n_ctiles * a.tile_cols;
   a.n_tiles = (int32_t)((a.NP + kTileRows - 1) / kTileRows);

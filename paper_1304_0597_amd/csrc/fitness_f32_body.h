@@ -65,8 +65,7 @@ __host__ __device__ constexpr int fit_waves(int cb) { return cb == 4 ? 8 : 4; }
 // chromosome].  genes: the chromosomes being scored; lds: the workgroup's
 // dynamic LDS.  D is the degree.  BASIS is the expansion family (kTrigTable:
 // the trigonometric one seeded from the stored (cos x, sin x) table a_in.cs
-// instead of sincosf in every tile).  CB = 4 needs the whole K in one chunk
-// (n_chunks == 1): its two wave groups walk different numbers of tiles.
+// instead of sincosf in every tile).
 template <int BASIS, int D, int CB = 2>
 __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const float* __restrict__ genes,
                                                   int split, int ctile, float* lds) {
@@ -83,7 +82,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   a.U = uniform(a_in.U);
   a.Q = uniform(a_in.Q);
   a.pairs_per_chunk = uniform(a_in.pairs_per_chunk);
-  a.n_chunks = CB == 4 ? 1 : uniform(a_in.n_chunks);
+  a.n_chunks = uniform(a_in.n_chunks);
   a.ld_partial = uniform(a_in.ld_partial);
   a.tiles_per_split = uniform(a_in.tiles_per_split);
   a.n_tiles = uniform(a_in.n_tiles);
@@ -203,7 +202,15 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   int st = 0;
   if (a.n_chunks > 1 && tile_begin < tile_end) stage_issue(0, 0);
 
-  for (int tile = tile_begin + wg; tile < tile_end; tile += TS) {
+  // Every wave takes the same number of steps of TS tiles.  A wave whose
+  // stream has no tile left in the last step leaves at once when the genes
+  // are staged once, and otherwise still joins the staging barriers of each
+  // chunk but computes nothing.
+  const int n_steps = (tile_end - tile_begin + TS - 1) / TS;
+  for (int step = 0; step < n_steps; ++step) {
+    const int tile = tile_begin + step * TS + wg;
+    const bool active = tile < tile_end;
+    if (!active && a.n_chunks == 1) break;
     const int64_t row0 = (int64_t)tile * kTileRows + wq * 64;
     // Rows past the data take a zero A operand in every K-step (bias step
     // included), so their residuals are exactly zero and the epilogue needs
@@ -218,7 +225,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
       const int64_t r = row0 + rb * 32 + m;
-      nt[rb] = r < NP ? -global_f32(a.t)[r] : 0.f;
+      nt[rb] = active && r < NP ? -global_f32(a.t)[r] : 0.f;
     }
     // Accumulators start at zero (an inline constant, nothing to keep live
     // across tiles).
@@ -236,10 +243,11 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
         __syncthreads();
         if (chunk + 1 < a.n_chunks) stage_issue(chunk + 1, (st + 1) & 1);
-        else if (tile + TS < tile_end) stage_issue(0, (st + 1) & 1);
+        else if (step + 1 < n_steps) stage_issue(0, (st + 1) & 1);
         wbuf = lds + (st & 1) * BUF;
         ++st;
       }
+      if (!active) continue;
       const int q_begin = chunk * ppc;
       const int q_end = min(q_begin + ppc, a.Q);
       for (int q = q_begin; q < q_end; ++q) {
@@ -283,6 +291,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
       }
     }
 
+    if (!active) continue;
     // Bias and target K-step: lane half 0 multiplies 1 by a0 of its column,
     // half 1 multiplies -t of its row by 1, so the accumulators end at
     // Out - t (0 for rows past the data).

@@ -62,8 +62,9 @@ SHAPES = [
     # few chromosomes over many patterns: hundreds of pattern splits
     (300001, 4, 2, 10),
     # 128-chromosome tiles over splits of 4 pattern tiles and a last split
-    # of 3 (the two wave groups of a workgroup walk unequal tile counts)
-    (100000, 5, 3, 200),
+    # of 3 (the two wave groups of a workgroup walk unequal tile counts),
+    # with the genes in one chunk and in chunks (180 K-steps per lane half)
+    (100000, 5, 3, 200), (100000, 40, 9, 150),
     # K-chunks through the two gene buffers over several tiles per split,
     # odd sub-feature count (zeroed half pair in the last chunk)
     (8000, 33, 10, 1100),
