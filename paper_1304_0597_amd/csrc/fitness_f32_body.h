@@ -106,7 +106,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wq = wave & 3;            // 64-row slice of a tile
-  const int wg = wave >> 2;           // tile stream
+  const int wg = TS == 1 ? 0 : wave >> 2;  // tile stream
   const int m = lane & 31;
   const int h = lane >> 5;
   const int c0 = ctile * kCols;
@@ -209,7 +209,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   const int n_steps = (tile_end - tile_begin + TS - 1) / TS;
   for (int step = 0; step < n_steps; ++step) {
     const int tile = tile_begin + step * TS + wg;
-    const bool active = tile < tile_end;
+    const bool active = TS == 1 || tile < tile_end;   // one stream: every step has its tile
     if (!active && a.n_chunks == 1) break;
     const int64_t row0 = (int64_t)tile * kTileRows + wq * 64;
     // Rows past the data take a zero A operand in every K-step (bias step
