@@ -34,7 +34,11 @@ using ConstItem = __attribute__((address_space(4))) const BatchItem;
 // 16 compile-time degrees, all inlined, so the kernel makes no calls (a call
 // per item would save and restore the callee's registers in private memory
 // every time).  A compile-time family keeps each body's expansion step the
-// fixed recurrence of that family.
+// fixed recurrence of that family.  Each wave takes two consecutive pattern
+// tiles at a time (four 32-row blocks over 64 chromosomes): a gene value
+// read from LDS then feeds four MFMAs, and chunked genes are restaged once
+// per two tiles; the per-element arithmetic and each tile's float32 sum
+// are the single run's.
 template <int BASIS>
 __device__ __forceinline__ void item_body(const ConstRun* run, const float* genes,
                                           int split, int ctile, float* lds) {
@@ -63,7 +67,7 @@ __device__ __forceinline__ void item_body(const ConstRun* run, const float* gene
   switch (__builtin_amdgcn_readfirstlane(run->D)) {
 #define GAME_CASE(D) \
   case D:            \
-    fitness_f32_block<BASIS, D>(fa, genes, split, ctile, lds); \
+    fitness_f32_block<BASIS, D, 2, 4>(fa, genes, split, ctile, lds); \
     break;
     GAME_CASE(1) GAME_CASE(2) GAME_CASE(3) GAME_CASE(4) GAME_CASE(5) GAME_CASE(6)
     GAME_CASE(7) GAME_CASE(8) GAME_CASE(9) GAME_CASE(10) GAME_CASE(11) GAME_CASE(12)

@@ -62,11 +62,12 @@ __host__ __device__ constexpr int fit_waves(int cb) { return cb == 4 ? 8 : 4; }
 
 // Tile range [split's tiles] x chromosome tile ctile (32*CB chromosomes) of
 // the launch described by a_in; writes a.partial[split * ld_partial +
-// chromosome].  genes: the chromosomes being scored; lds: the workgroup's
-// dynamic LDS.  D is the degree.  BASIS is the expansion family (kTrigTable:
-// the trigonometric one seeded from the stored (cos x, sin x) table a_in.cs
-// instead of sincosf in every tile).
-template <int BASIS, int D, int CB = 2>
+// chromosome].  Each wave takes RB/2 consecutive 256-row tiles at a time
+// (its 64-row slice of each: RB 32-row blocks).  genes: the chromosomes
+// being scored; lds: the workgroup's dynamic LDS.  D is the degree.  BASIS
+// is the expansion family (kTrigTable: the trigonometric one seeded from
+// the stored (cos x, sin x) table a_in.cs instead of sincosf in every tile).
+template <int BASIS, int D, int CB = 2, int RB = 2>
 __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const float* __restrict__ genes,
                                                   int split, int ctile, float* lds) {
   // The parameters the body uses, read once into scalar registers (so that
@@ -101,7 +102,10 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   lds = uniform(lds);
   static_assert(CB == 2 || CB == 4, "64- or 128-chromosome tiles");
   constexpr int NW = fit_waves(CB);   // waves per workgroup
-  constexpr int TS = NW / 4;          // row tiles in flight (tile stride)
+  constexpr int TS = NW / 4;          // tile streams (wave groups)
+  static_assert(RB == 2 || RB == 4, "one or two 256-row tiles per wave");
+  constexpr int TPW = RB / 2;         // consecutive row tiles per wave
+  constexpr int STEP = TS * TPW;      // row tiles per step of the workgroup
   constexpr int kCols = 32 * CB;      // chromosomes per tile
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -171,13 +175,18 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
 
   // x of sub-feature pair q for this lane's two rows (0 outside the data);
   // from the stored trig table, cos x into xo and sin x into so instead.
-  auto load_x = [&](int64_t row0, int q, float (&xo)[2], float (&so)[2]) {
+  // Row of block rb of the wave whose first tile is `tile`: blocks 2i and
+  // 2i+1 are the wave's 64-row slice of tile + i.
+  auto row_of = [&](int tile, int rb) -> int64_t {
+    return (int64_t)(tile + rb / 2) * kTileRows + wq * 64 + (rb & 1) * 32 + m;
+  };
+  auto load_x = [&](int tile, int q, float (&xo)[RB], float (&so)[RB]) {
     if constexpr (kTable) {
       typedef float f32x2 __attribute__((ext_vector_type(2)));
       typedef const f32x2 __attribute__((address_space(1)))* gptr_f32x2;
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        const int64_t r = row0 + rb * 32 + m;
+      for (int rb = 0; rb < RB; ++rb) {
+        const int64_t r = row_of(tile, rb);
         f32x2 v = {0.f, 0.f};
         if (r < NP) v = ((gptr_f32x2)a.cs)[r * N + q];
         xo[rb] = v.x;
@@ -189,49 +198,51 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
     const int f = trig ? q : u;
     const bool fvalid = trig ? true : (u < a.U);
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-      const int64_t r = row0 + rb * 32 + m;
+    for (int rb = 0; rb < RB; ++rb) {
+      const int64_t r = row_of(tile, rb);
       xo[rb] = (r < NP && fvalid) ? global_f32(a.X)[r * N + f] : 0.f;
     }
   };
 
-  float xn[2] = {0.f, 0.f}, sn[2] = {0.f, 0.f};
-  if (tile_begin + wg < tile_end) load_x((int64_t)(tile_begin + wg) * kTileRows + wq * 64, 0, xn, sn);
+  float xn[RB], sn[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) xn[rb] = sn[rb] = 0.f;
+  if (tile_begin + wg * TPW < tile_end) load_x(tile_begin + wg * TPW, 0, xn, sn);
   // Chunked genes: stage index st runs over (tile, chunk) in loop order and
   // uses buffer st & 1.
   int st = 0;
   if (a.n_chunks > 1 && tile_begin < tile_end) stage_issue(0, 0);
 
-  // Every wave takes the same number of steps of TS tiles.  A wave whose
+  // Every wave takes the same number of steps of STEP tiles.  A wave whose
   // stream has no tile left in the last step leaves at once when the genes
   // are staged once, and otherwise still joins the staging barriers of each
   // chunk but computes nothing.
-  const int n_steps = (tile_end - tile_begin + TS - 1) / TS;
+  const int n_steps = (tile_end - tile_begin + STEP - 1) / STEP;
   for (int step = 0; step < n_steps; ++step) {
-    const int tile = tile_begin + step * TS + wg;
+    const int tile = tile_begin + step * STEP + wg * TPW;   // the wave's first tile
     const bool active = TS == 1 || tile < tile_end;   // one stream: every step has its tile
     if (!active && a.n_chunks == 1) break;
-    const int64_t row0 = (int64_t)tile * kTileRows + wq * 64;
     // Rows past the data take a zero A operand in every K-step (bias step
     // included), so their residuals are exactly zero and the epilogue needs
     // no row mask.
-    bool row_ok[2];
+    bool row_ok[RB];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) row_ok[rb] = row0 + rb * 32 + m < NP;
+    for (int rb = 0; rb < RB; ++rb)
+      row_ok[rb] = (RB == 2 || tile + rb / 2 < tile_end) && row_of(tile, rb) < NP;
     // Minus the targets of this lane's rows (0 past the data); they join
     // with the bias in a last K-step, so the load's latency hides behind the
     // K loop.
-    float nt[2];
+    float nt[RB];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-      const int64_t r = row0 + rb * 32 + m;
-      nt[rb] = active && r < NP ? -global_f32(a.t)[r] : 0.f;
+    for (int rb = 0; rb < RB; ++rb) {
+      const int64_t r = row_of(tile, rb);
+      nt[rb] = active && row_ok[rb] ? -global_f32(a.t)[r] : 0.f;
     }
     // Accumulators start at zero (an inline constant, nothing to keep live
     // across tiles).
-    f32x16 acc[2][CB];
+    f32x16 acc[RB][CB];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = f32x16{};
 
@@ -251,13 +262,18 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
       const int q_begin = chunk * ppc;
       const int q_end = min(q_begin + ppc, a.Q);
       for (int q = q_begin; q < q_end; ++q) {
-        float x[2] = {xn[0], xn[1]}, sx[2] = {sn[0], sn[1]};
-        // prefetch the next pair, or the first pair of the next tile
-        if (q + 1 < a.Q) load_x(row0, q + 1, xn, sn);
-        else if (tile + TS < tile_end) load_x(row0 + TS * kTileRows, 0, xn, sn);
-        Recur<FAM> rc[2];
+        float x[RB], sx[RB];
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
+        for (int rb = 0; rb < RB; ++rb) {
+          x[rb] = xn[rb];
+          sx[rb] = sn[rb];
+        }
+        // prefetch the next pair, or the first pair of the next tile
+        if (q + 1 < a.Q) load_x(tile, q + 1, xn, sn);
+        else if (tile + STEP < tile_end) load_x(tile + STEP, 0, xn, sn);
+        Recur<FAM> rc[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
           if constexpr (kTable) {
             rc[rb].seed_cs(x[rb], sx[rb], h);
           } else {
@@ -274,13 +290,13 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) b[cb] = wl[cb * 32 * WS + j];
 #pragma unroll
-          for (int rb = 0; rb < 2; ++rb)
+          for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb)
               acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(rc[rb].cur, b[cb], acc[rb][cb], 0, 0, 0);
           if constexpr (j + 1 < D) {
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
+            for (int rb = 0; rb < RB; ++rb) {
               rc[rb].template advance<j + 1>(x[rb]);
             }
           }
@@ -296,7 +312,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
     // half 1 multiplies -t of its row by 1, so the accumulators end at
     // Out - t (0 for rows past the data).
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
+    for (int rb = 0; rb < RB; ++rb) {
       const float ab = h ? nt[rb] : (row_ok[rb] ? 1.f : 0.f);
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
@@ -307,23 +323,31 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
     // lane's 32 rows (register order; accumulator register i of row block rb
     // holds row rb*32 + 8*(i/4) + 4*h + i%4 of the wave's 64 rows).  Rows
     // past the data add exactly zero.
-    float s[CB];
+    // One float32 sum per row tile (its two row blocks), added to the
+    // float64 running sum tile by tile, so that a tile's sum does not
+    // depend on how many tiles a wave takes at once.
+    float s[TPW][CB];
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) s[cb] = 0.f;
+    for (int tp = 0; tp < TPW; ++tp)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) s[tp][cb] = 0.f;
     auto epilogue = [&](auto mode_c) {
       constexpr int mode = decltype(mode_c)::value;
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int i = 0; i < 16; ++i)
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) s[cb] = add_error_term<mode>(s[cb], acc[rb][cb][i], a.R);
+          for (int cb = 0; cb < CB; ++cb)
+            s[rb / 2][cb] = add_error_term<mode>(s[rb / 2][cb], acc[rb][cb][i], a.R);
     };
     if (a.error_fn == 2) epilogue(std::integral_constant<int, 2>{});
     else if (a.error_fn == 3) epilogue(std::integral_constant<int, 3>{});
     else epilogue(std::integral_constant<int, 0>{});
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) acc64[cb] += (double)s[cb];
+    for (int tp = 0; tp < TPW; ++tp)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc64[cb] += (double)s[tp][cb];
   }
 
   // Combine the two lane halves (same chromosome, different rows), then the
