@@ -112,6 +112,20 @@ __device__ __forceinline__ uint64_t rank_key(float f, int i) {
   return ((uint64_t)ordered_bits(rank_key_value(f)) << 32) | (uint32_t)i;
 }
 
+// keys[i] = rank_key(fit[i], i) for i < P; the workgroup's loads of up to
+// four keys per thread are in flight together.
+__device__ __forceinline__ void fill_rank_keys(const float* fit, int P, uint64_t* keys) {
+  const int nb = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < P; i0 += 4 * nb) {
+    float f[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) f[u] = i0 + u * nb < P ? fit[i0 + u * nb] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + u * nb < P) keys[i0 + u * nb] = rank_key(f[u], i0 + u * nb);
+  }
+}
+
 __device__ __forceinline__ int count_rank(const uint64_t* keys, int P, int e, uint32_t* cnt) {
   constexpr int parts = kRankThreads / kRankPerBlock;
   const int part = threadIdx.x / kRankPerBlock;
@@ -121,7 +135,17 @@ __device__ __forceinline__ int count_rank(const uint64_t* keys, int P, int e, ui
     const int per = (P + parts - 1) / parts;
     const int j0 = part * per;
     const int j1 = min(j0 + per, P);
-    for (int j = j0; j < j1; ++j) c += keys[j] < ke ? 1u : 0u;
+    // Eight LDS reads in flight before the first compare (a read-compare
+    // loop waits out the LDS latency for every key).
+    int j = j0;
+    for (; j + 8 <= j1; j += 8) {
+      uint64_t kj[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) kj[u] = keys[j + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) c += kj[u] < ke ? 1u : 0u;
+    }
+    for (; j < j1; ++j) c += keys[j] < ke ? 1u : 0u;
   }
   cnt[threadIdx.x] = c;
   __syncthreads();
@@ -138,7 +162,7 @@ __global__ __launch_bounds__(kRankThreads) void rank_kernel(const float* __restr
                                                             int32_t* __restrict__ order) {
   extern __shared__ uint64_t keys[];
   __shared__ uint32_t cnt[kRankThreads];
-  for (int i = threadIdx.x; i < n; i += blockDim.x) keys[i] = rank_key(fit[i], i);
+  fill_rank_keys(fit, n, keys);
   __syncthreads();
   const int e = blockIdx.x * kRankPerBlock + (threadIdx.x % kRankPerBlock);
   const int r = count_rank(keys, n, e, cnt);
@@ -160,10 +184,43 @@ hipError_t launch_rank(const float* fit, int32_t n, int32_t* order, hipStream_t 
 }
 
 // Errors of the 64 chromosomes [blk*64, blk*64+64) from their split
-// partials, one wave per chromosome (4 waves per workgroup).
+// partials, one wave per chromosome at a time (16 waves per workgroup, four
+// chromosomes each).  With at most 64 splits a wave first loads the
+// partials of all its chromosomes (lane l: split l, as wave_split_sum reads
+// it), then adds each with the same butterfly, so the loads share one round
+// trip.
+constexpr int kReduceWaves = 16;
 __device__ void reduce_fitness_body(const RankArgs& a, int blk) {
   if (a.state->stop_seen) return;
   const int waves = blockDim.x >> 6;
+  if (a.n_splits <= 64 && waves == kReduceWaves) {
+    constexpr int kPer = kRankPerBlock / kReduceWaves;
+    const int lane = threadIdx.x & 63;
+    const int i0 = blk * kRankPerBlock + (int)(threadIdx.x >> 6);
+    double v[kPer];
+#pragma unroll
+    for (int c = 0; c < kPer; ++c) {
+      // Unconditional loads (element 0 where there is no partial), so that
+      // no branch separates them.
+      const int i = i0 + c * kReduceWaves;
+      const bool ok = i < a.P && lane < a.n_splits;
+      const double p = a.partial[ok ? (int64_t)lane * a.ld_partial + i : 0];
+      v[c] = ok ? 0.0 + p : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < kPer; ++c) {
+      const int i = i0 + c * kReduceWaves;
+      if (i >= a.P) break;
+      double s = v[c];
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+      const double e = error_from_sum(s, a.NP, a.error_fn);
+      if (lane == 0) {
+        a.fit64[i] = e;
+        a.fit32[i] = (float)e;
+      }
+    }
+    return;
+  }
   for (int j = (int)(threadIdx.x >> 6); j < kRankPerBlock; j += waves) {
     const int i = blk * kRankPerBlock + j;
     if (i >= a.P) break;
@@ -176,13 +233,13 @@ __device__ void reduce_fitness_body(const RankArgs& a, int blk) {
   }
 }
 
-__global__ __launch_bounds__(256) void reduce_fitness_kernel(RankArgs a) {
+__global__ __launch_bounds__(64 * kReduceWaves) void reduce_fitness_kernel(RankArgs a) {
   reduce_fitness_body(a, blockIdx.x);
 }
 
 hipError_t launch_reduce_fitness(const RankArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(reduce_fitness_kernel, dim3((a.P + kRankPerBlock - 1) / kRankPerBlock),
-                     dim3(256), 0, s, a);
+                     dim3(64 * kReduceWaves), 0, s, a);
   return hipGetLastError();
 }
 
@@ -198,7 +255,7 @@ __device__ void finish_rank_body(const RankArgs& a, int blk, uint64_t* keys, uin
   if (st->stop_seen) return;
   const int P = a.P;
   const int lo = blk * kRankPerBlock;
-  for (int i = threadIdx.x; i < P; i += blockDim.x) keys[i] = rank_key(a.fit32[i], i);
+  fill_rank_keys(a.fit32, P, keys);
   __syncthreads();
   const int e = lo + (threadIdx.x % kRankPerBlock);
   const int r = count_rank(keys, P, e, cnt);
@@ -292,19 +349,40 @@ struct PairWords {
   }
 };
 
-// Tournament of k draws, words [w0, w0 + k) of the pair.
-__device__ __forceinline__ int tournament(const float* fit, PairWords& w, int w0, int k, int P) {
-  int best = (int)(((uint64_t)w(w0) * (uint64_t)P) >> 32);
-  float fb = fit_at(fit, best);
-  for (int c = 1; c < k; ++c) {
-    const int cand = (int)(((uint64_t)w(w0 + c) * (uint64_t)P) >> 32);
-    const float fc = fit_at(fit, cand);
-    if (fc < fb || (fc == fb && cand < best)) {
-      best = cand;
-      fb = fc;
+// Both tournaments of a pair: words [0, k) draw parent 1's candidates and
+// [k, 2k) parent 2's.  The best candidate is the lowest fitness, ties to
+// the lower index, the first draw kept unless beaten.  Candidate fitness
+// values are loaded eight at a time, so their loads share a round trip;
+// the comparisons run in draw order.
+__device__ __forceinline__ void tournament_pair(const float* fit, PairWords& w, int k, int P,
+                                                int& p1, int& p2) {
+  int b1 = -1, b2 = -1;
+  float f1 = 0.f, f2 = 0.f;
+  for (int c0 = 0; c0 < 2 * k; c0 += 8) {
+    int cand[8];
+    float fc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      cand[u] = c0 + u < 2 * k ? (int)(((uint64_t)w(c0 + u) * (uint64_t)P) >> 32) : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) fc[u] = fit_at(fit, cand[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = c0 + u;
+      if (c >= 2 * k) break;
+      if (c < k) {
+        if (b1 < 0 || fc[u] < f1 || (fc[u] == f1 && cand[u] < b1)) {
+          b1 = cand[u];
+          f1 = fc[u];
+        }
+      } else if (b2 < 0 || fc[u] < f2 || (fc[u] == f2 && cand[u] < b2)) {
+        b2 = cand[u];
+        f2 = fc[u];
+      }
     }
   }
-  return best;
+  p1 = b1;
+  p2 = b2;
 }
 
 // Linear ranking, pressure 2: rank r has weight P - r; the integer draw
@@ -421,8 +499,7 @@ __device__ __forceinline__ void ga_next_wave(const GAArgs& a, int wid) {
     p1 = roulette_pick(a.cum, P, w(0));
     p2 = roulette_pick(a.cum, P, w(1));
   } else {
-    p1 = tournament(a.fitness, w, 0, k, P);
-    p2 = tournament(a.fitness, w, k, k, P);
+    tournament_pair(a.fitness, w, k, P, p1, p2);
   }
   const bool cross = (uint64_t)w(2 * k) < a.thr_cross;
   const int cut = 1 + (int)(((uint64_t)w(2 * k + 1) * (uint64_t)(K - 1)) >> 32);
@@ -433,23 +510,36 @@ __device__ __forceinline__ void ga_next_wave(const GAArgs& a, int wid) {
                                    out + (int64_t)sa * K);
   float* __restrict__ out_b = pick(a.children != nullptr, a.children + (int64_t)(sb - E) * K,
                                    out + (int64_t)sb * K);
-  for (int g = lane; g < K; g += 64) {
-    const float x1 = pop[(int64_t)p1 * K + g];
-    const float x2 = pop[(int64_t)p2 * K + g];
-    const bool sw = cross && g >= cut;
-    float ca = sw ? x2 : x1;
-    float cb = sw ? x1 : x2;
-    {
-      const U64x4 r = draw(a.seed, 2, (uint64_t)gen, (uint64_t)sa, (uint64_t)g);
-      if ((r.o0 & 0xFFFFFFFFull) < a.thr_mut)
-        ca = clamp_unit(__fadd_rn(ca, __fmul_rn(a.sigma, gauss12(r))));
+  // The parents' genes of up to four lane strides are loaded before the
+  // mutation draws, so the loads' latency overlaps the draws.
+  constexpr int kStrides = 4;
+  for (int g0 = lane; g0 < K; g0 += kStrides * 64) {
+    float x1[kStrides], x2[kStrides];
+#pragma unroll
+    for (int u = 0; u < kStrides; ++u) {
+      const int g = g0 + 64 * u;
+      x1[u] = g < K ? pop[(int64_t)p1 * K + g] : 0.f;
+      x2[u] = g < K ? pop[(int64_t)p2 * K + g] : 0.f;
     }
-    out_a[g] = ca;
-    if (has_b) {
-      const U64x4 r = draw(a.seed, 2, (uint64_t)gen, (uint64_t)sb, (uint64_t)g);
-      if ((r.o0 & 0xFFFFFFFFull) < a.thr_mut)
-        cb = clamp_unit(__fadd_rn(cb, __fmul_rn(a.sigma, gauss12(r))));
-      out_b[g] = cb;
+#pragma unroll
+    for (int u = 0; u < kStrides; ++u) {
+      const int g = g0 + 64 * u;
+      if (g >= K) break;
+      const bool sw = cross && g >= cut;
+      float ca = sw ? x2[u] : x1[u];
+      float cb = sw ? x1[u] : x2[u];
+      {
+        const U64x4 r = draw(a.seed, 2, (uint64_t)gen, (uint64_t)sa, (uint64_t)g);
+        if ((r.o0 & 0xFFFFFFFFull) < a.thr_mut)
+          ca = clamp_unit(__fadd_rn(ca, __fmul_rn(a.sigma, gauss12(r))));
+      }
+      out_a[g] = ca;
+      if (has_b) {
+        const U64x4 r = draw(a.seed, 2, (uint64_t)gen, (uint64_t)sb, (uint64_t)g);
+        if ((r.o0 & 0xFFFFFFFFull) < a.thr_mut)
+          cb = clamp_unit(__fadd_rn(cb, __fmul_rn(a.sigma, gauss12(r))));
+        out_b[g] = cb;
+      }
     }
   }
 }
@@ -491,14 +581,15 @@ __global__ __launch_bounds__(kRankThreads) void finish_rank_batch_kernel(BatchAr
   finish_rank_body(rank_args_of(run), blockIdx.x - run.rank_block0, keys, cnt);
 }
 
-__global__ __launch_bounds__(256) void reduce_fitness_batch_kernel(BatchArgs a) {
+__global__ __launch_bounds__(64 * kReduceWaves) void reduce_fitness_batch_kernel(BatchArgs a) {
   const int r = a.rank_block_run[blockIdx.x];
   const BatchRun& run = a.runs[r];
   reduce_fitness_body(rank_args_of(run), blockIdx.x - run.rank_block0);
 }
 
 hipError_t launch_reduce_fitness_batch(const BatchArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(reduce_fitness_batch_kernel, dim3(a.n_rank_blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(reduce_fitness_batch_kernel, dim3(a.n_rank_blocks), dim3(64 * kReduceWaves), 0,
+                     s, a);
   return hipGetLastError();
 }
 

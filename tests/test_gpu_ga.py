@@ -294,3 +294,33 @@ def test_selection_modes_in_the_loop(gg, selection):
         ref_next = oga.ga_next(pop_g, fit_g, gen + 1, ocfg)
         assert np.array_equal(bits(pop_next), bits(ref_next)), gen
     g.close()
+
+
+# (NP, N, d, P) and the pattern splits the plan gives them: at most 64 and
+# more than 64, with 64- and 128-chromosome tiles, ragged last workgroups.
+SPLIT_SHAPES = [((2000, 7, 4, 50), "8-splits"), ((5000, 8, 4, 300), "20-splits-128-wide"),
+                ((100000, 5, 3, 50), "391-splits"), ((40000, 8, 4, 300), "79-splits-128-wide")]
+
+
+@pytest.mark.parametrize("error_fn", [0, 1], ids=["MSE", "RMSE"])
+@pytest.mark.parametrize("shape", [s for s, _ in SPLIT_SHAPES], ids=[i for _, i in SPLIT_SHAPES])
+def test_step_errors_are_the_fitness_launch_bits(gg, shape, error_fn):
+    """The errors a generation records (its split partials reduced by the
+    evaluation epilogue) equal game_fitness on the same population bit for
+    bit: both add the same partials in the same order, on the path for at
+    most 64 splits and on the one for more."""
+    NP, N, d, P = shape
+    rng = np.random.default_rng(NP + P)
+    X = torch.from_numpy(rng.uniform(-1, 1, (NP, N)).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.normal(0, 1, NP).astype(np.float32)).cuda()
+    c = gg.config(basis=1, degree=d, population=P, seed=5, max_generations=100, target=0.0,
+                  error_fn=error_fn)
+    g = gg.Game(c, X, t)
+    g.init_population()
+    for _ in range(2):
+        pop, _ = g.population()
+        g.step()
+        _, fit = g.population()
+        ref = g.fitness(pop)
+        assert np.array_equal(bits(fit.cpu().numpy()), bits(ref.cpu().numpy()))
+    g.close()
