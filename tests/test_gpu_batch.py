@@ -122,6 +122,37 @@ def test_autotune_leaves_populations_and_picks_a_candidate(gg):
     b2.close()
 
 
+# Edges of the two-tile waves: a run under one pattern tile, exactly two
+# full tiles, three tiles (a wave's second tile missing in the last step),
+# degree 1, a population over many chromosome tiles, chunked genes.
+EDGE_RUNS = [(100, 3, 5, 40, 0), (512, 6, 1, 64, 2), (768, 9, 4, 1000, 1), (60, 40, 9, 70, 3),
+             (1900, 48, 10, 65, 1)]
+
+
+@pytest.mark.parametrize("tiles,grid", [(None, None), (1, 256), (3, 512)],
+                         ids=["default", "1-tile-items", "3-tile-items"])
+def test_batch_edges_equal_single_runs(gg, tiles, grid):
+    problems, cfgs, _ = make_runs(gg, runs=EDGE_RUNS, max_gen=4, seed0=31)
+    b = gg.Batch(problems, cfgs)
+    if tiles is not None:
+        b.tune(tiles, grid)
+    b.init()
+    gens, best = b.run()
+    assert np.all(gens == 4)
+    for r, c in enumerate(cfgs):
+        g = gg.Game(c, *problems[r])
+        g.init_population()
+        n, _, err = g.run()
+        assert n == 4
+        pb, fb = b.population(r)
+        ps, fs = g.population()
+        assert np.array_equal(bits(pb.cpu().numpy()), bits(ps.cpu().numpy())), r
+        assert np.array_equal(bits(fb.cpu().numpy()), bits(fs.cpu().numpy())), r
+        assert best[r] == err, r
+        g.close()
+    b.close()
+
+
 @pytest.mark.parametrize("tiles,grid", [(1, 64), (32, 1024), (3, 7)])
 def test_any_decomposition_gives_the_same_trajectory(gg, tiles, grid):
     problems, cfgs, _ = make_runs(gg, runs=RUNS[:4], max_gen=3)
