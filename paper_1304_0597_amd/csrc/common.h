@@ -416,7 +416,7 @@ hipError_t launch_audit_pick(const float* cand, int32_t C, int32_t K, const RunS
 // (float64 moments summed in a fixed order, population form, the standard
 // deviation floored at kInputStdFloor): part holds 2 * kMomentBlocks * K
 // doubles.
-constexpr int kMomentBlocks = 64;
+constexpr int kMomentBlocks = 256;   // a multiple of kMomentRows (16)
 constexpr double kInputStdFloor = 1e-3;
 hipError_t launch_gene_stats(const float* genes, int32_t K, int32_t capacity,
                              const SurrogateState* st, const RunState* run, double* part,

@@ -784,11 +784,13 @@ hipError_t launch_archive_stats(const float* target, SurrogateState* st, const R
 // its archive spread, so that the network resolves the small differences
 // between a converging population's chromosomes.  Workgroup b sums rows
 // [b * per, (b + 1) * per) of the archive per gene in float64 (one thread
-// per gene, rows in order: coalesced reads of each row); then one thread
-// per gene adds the kMomentBlocks shares in workgroup order.
-__global__ __launch_bounds__(256) void gene_moments_kernel(const float* genes, int K, int capacity,
-                                                          const SurrogateState* st,
-                                                          const RunState* run, double* part) {
+// per gene, rows in order: coalesced reads of each row, 16 rows' loads in
+// flight at a time); then one thread per gene adds the kMomentBlocks shares
+// in workgroup order.
+constexpr int kMomentRows = 16;
+__global__ __launch_bounds__(1024) void gene_moments_kernel(const float* genes, int K, int capacity,
+                                                           const SurrogateState* st,
+                                                           const RunState* run, double* part) {
   if (run->stop) return;
   const int count = st->count;
   const int per = (capacity + kMomentBlocks - 1) / kMomentBlocks;
@@ -796,7 +798,19 @@ __global__ __launch_bounds__(256) void gene_moments_kernel(const float* genes, i
   const int r1 = min(r0 + per, count);
   for (int g = threadIdx.x; g < K; g += blockDim.x) {
     double a = 0.0, b = 0.0;
-    for (int r = r0; r < r1; ++r) {
+    int r = r0;
+    for (; r + kMomentRows <= r1; r += kMomentRows) {
+      float v[kMomentRows];
+#pragma unroll
+      for (int u = 0; u < kMomentRows; ++u) v[u] = genes[(int64_t)(r + u) * K + g];
+#pragma unroll
+      for (int u = 0; u < kMomentRows; ++u) {
+        const double d = v[u];
+        a += d;
+        b += d * d;
+      }
+    }
+    for (; r < r1; ++r) {
       const double v = genes[(int64_t)r * K + g];
       a += v;
       b += v * v;
@@ -813,9 +827,18 @@ __global__ void gene_stats_kernel(const double* part, int K, const SurrogateStat
   const int count = st->count;
   if (g >= K || count < 1) return;
   double a = 0.0, b = 0.0;
-  for (int k = 0; k < kMomentBlocks; ++k) {
-    a += part[(int64_t)k * K + g];
-    b += part[(int64_t)(kMomentBlocks + k) * K + g];
+  for (int k0 = 0; k0 < kMomentBlocks; k0 += kMomentRows) {
+    double pa[kMomentRows], pb[kMomentRows];
+#pragma unroll
+    for (int u = 0; u < kMomentRows; ++u) {
+      pa[u] = part[(int64_t)(k0 + u) * K + g];
+      pb[u] = part[(int64_t)(kMomentBlocks + k0 + u) * K + g];
+    }
+#pragma unroll
+    for (int u = 0; u < kMomentRows; ++u) {
+      a += pa[u];
+      b += pb[u];
+    }
   }
   const double m = a / count;
   const double var = fmax(b / count - m * m, 0.0);
@@ -826,8 +849,9 @@ __global__ void gene_stats_kernel(const double* part, int K, const SurrogateStat
 hipError_t launch_gene_stats(const float* genes, int32_t K, int32_t capacity,
                              const SurrogateState* st, const RunState* run, double* part,
                              float* mu, float* inv, hipStream_t s) {
-  hipLaunchKernelGGL(gene_moments_kernel, dim3(kMomentBlocks), dim3(256), 0, s, genes, K, capacity,
-                     st, run, part);
+  const int threads = min(1024, (K + 63) / 64 * 64);
+  hipLaunchKernelGGL(gene_moments_kernel, dim3(kMomentBlocks), dim3(threads), 0, s, genes, K,
+                     capacity, st, run, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(gene_stats_kernel, dim3((K + 255) / 256), dim3(256), 0, s, part, K, st, run,
