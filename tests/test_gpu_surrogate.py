@@ -194,14 +194,16 @@ def test_fallback_reproduces_the_plain_run(gg):
     s.close()
 
 
+@pytest.mark.parametrize("nf,d", [(10, 6), (130, 8)], ids=["61-genes", "1041-genes"])
 @pytest.mark.parametrize("fp32", [True, False])
-def test_input_stats_follow_the_archive(gg, fp32):
+def test_input_stats_follow_the_archive(gg, fp32, nf, d):
     """The network's inputs are the genes standardised with the archive's
     per-gene mean and inverse deviation.  After five screened generations
     (the archive holds all of them) the device statistics equal the oracle's
     over those five populations, and a prediction equals the float64
-    network on the oracle-standardised genes."""
-    prob = _problem(n=3000)
+    network on the oracle-standardised genes.  With more than 1,024 genes
+    a statistics thread covers several genes."""
+    prob = _problem(n=3000, nf=nf, d=d)
     P = prob.population
     g = _game(gg, prob)
     s = make(gg, prob.n_genes, fp32, H=64, minibatch=128, max_batch=8 * (P - 2), rho_min=-1.0,
