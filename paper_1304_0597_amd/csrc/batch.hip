@@ -38,7 +38,10 @@ using ConstItem = __attribute__((address_space(4))) const BatchItem;
 // tiles at a time (four 32-row blocks over 64 chromosomes): a gene value
 // read from LDS then feeds four MFMAs, and chunked genes are restaged once
 // per two tiles; the per-element arithmetic and each tile's float32 sum
-// are the single run's.
+// are the single run's.  A run's last chromosome tile with at most 32 of
+// its chromosomes takes a 32-column body (one MFMA column block), so the
+// empty half of the tile is not computed; its index in 32-column units is
+// twice the 64-column one.
 template <int BASIS>
 __device__ __forceinline__ void item_body(const ConstRun* run, const float* genes,
                                           int split, int ctile, float* lds) {
@@ -64,10 +67,12 @@ __device__ __forceinline__ void item_body(const ConstRun* run, const float* gene
   fa.cs = run->cs;
   fa.degree = run->D;
   fa.basis = run->basis;
+  const bool narrow = run->P - ctile * kTileCols <= 32;
   switch (__builtin_amdgcn_readfirstlane(run->D)) {
-#define GAME_CASE(D) \
-  case D:            \
-    fitness_f32_block<BASIS, D, 2, 4>(fa, genes, split, ctile, lds); \
+#define GAME_CASE(D)                                                     \
+  case D:                                                                \
+    if (narrow) fitness_f32_block<BASIS, D, 1, 4>(fa, genes, split, 2 * ctile, lds); \
+    else fitness_f32_block<BASIS, D, 2, 4>(fa, genes, split, ctile, lds);            \
     break;
     GAME_CASE(1) GAME_CASE(2) GAME_CASE(3) GAME_CASE(4) GAME_CASE(5) GAME_CASE(6)
     GAME_CASE(7) GAME_CASE(8) GAME_CASE(9) GAME_CASE(10) GAME_CASE(11) GAME_CASE(12)

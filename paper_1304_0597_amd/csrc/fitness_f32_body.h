@@ -56,13 +56,13 @@ typedef const float __attribute__((address_space(1)))* gptr_f32;
 __device__ __forceinline__ gptr_f32 global_f32(const float* p) { return (gptr_f32)p; }
 
 // Waves per workgroup of the body with CB 32-column blocks per wave: four
-// for 64-chromosome tiles, eight for 128-chromosome tiles (waves 0-3 take
-// the even row tiles of the split and 4-7 the odd ones, two per SIMD).
+// for 32- and 64-chromosome tiles, eight for 128-chromosome tiles (waves 0-3
+// take the even row tiles of the split and 4-7 the odd ones, two per SIMD).
 __host__ __device__ constexpr int fit_waves(int cb) { return cb == 4 ? 8 : 4; }
 
-// Tile range [split's tiles] x chromosome tile ctile (32*CB chromosomes) of
-// the launch described by a_in; writes a.partial[split * ld_partial +
-// chromosome].  Each wave takes RB/2 consecutive 256-row tiles at a time
+// Tile range [split's tiles] x chromosome tile ctile (32*CB chromosomes,
+// the first one ctile * 32*CB) of the launch described by a_in; writes
+// a.partial[split * ld_partial + chromosome].  Each wave takes RB/2 consecutive 256-row tiles at a time
 // (its 64-row slice of each: RB 32-row blocks).  genes: the chromosomes
 // being scored; lds: the workgroup's dynamic LDS.  D is the degree.  BASIS
 // is the expansion family (kTrigTable: the trigonometric one seeded from
@@ -100,7 +100,7 @@ __device__ __forceinline__ void fitness_f32_block(const FitArgs& a_in, const flo
   split = uniform(split);
   ctile = uniform(ctile);
   lds = uniform(lds);
-  static_assert(CB == 2 || CB == 4, "64- or 128-chromosome tiles");
+  static_assert(CB == 1 || CB == 2 || CB == 4, "32-, 64- or 128-chromosome tiles");
   constexpr int NW = fit_waves(CB);   // waves per workgroup
   constexpr int TS = NW / 4;          // tile streams (wave groups)
   static_assert(RB == 2 || RB == 4, "one or two 256-row tiles per wave");
