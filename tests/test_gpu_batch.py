@@ -124,9 +124,10 @@ def test_autotune_leaves_populations_and_picks_a_candidate(gg):
 
 # Edges of the two-tile waves: a run under one pattern tile, exactly two
 # full tiles, three tiles (a wave's second tile missing in the last step),
-# degree 1, a population over many chromosome tiles, chunked genes.
+# degree 1, a population over many chromosome tiles, chunked genes, and the
+# smallest runs (one pattern and one feature; three patterns, trig).
 EDGE_RUNS = [(100, 3, 5, 40, 0), (512, 6, 1, 64, 2), (768, 9, 4, 1000, 1), (60, 40, 9, 70, 3),
-             (1900, 48, 10, 65, 1)]
+             (1900, 48, 10, 65, 1), (1, 1, 1, 4, 0), (3, 2, 2, 5, 3)]
 
 
 @pytest.mark.parametrize("tiles,grid", [(None, None), (1, 256), (3, 512)],
